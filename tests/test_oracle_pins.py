@@ -1,0 +1,538 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: published
+known-answer vectors, closed-form solutions, exact invariants, the paper's
+Eq. (1) values, or statistics with an analytic expectation (3-4 sigma bands).
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+from oracle import pyoracle as po
+from paper_0705_0497_amd import inputs as I
+
+QE, KB, EPS0 = 1.602176634e-19, 1.380649e-23, 8.8541878128e-12
+ME = I.ELECTRON_MASS
+TWO32 = 2 ** 32
+
+
+def species(ne=0, npos=0, nneg=0, te=3.0, ti=0.026):
+    return [I.Species(-1.0, ME, te, ne, max(ne, 1)), I.Species(1.0, I.M_O2PLUS, ti, npos, max(npos, 1)),
+            I.Species(-1.0, I.M_OMINUS, ti, nneg, max(nneg, 1))]
+
+
+def put(o, s, xi, vx, vy=None, vz=None, cd=None):
+    n = len(xi)
+    z = np.zeros(n)
+    o.set_particles64(s, dict(xi=np.asarray(xi, float), vx=np.asarray(vx, float),
+                              vy=z if vy is None else vy, vz=z if vz is None else vz,
+                              id=np.arange(n, dtype=np.uint32),
+                              cd=np.ones(n, np.int32) if cd is None else cd), next_id=n)
+
+
+def empty(o, s):
+    put(o, s, np.zeros(0), np.zeros(0))
+
+
+# ---------------------------------------------------------------- Philox
+@pytest.mark.parametrize("ctr,key,expect", [
+    ((0, 0, 0, 0), (0, 0), (0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8)),
+    ((0xffffffff,) * 4, (0xffffffff,) * 2, (0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd)),
+    ((0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344), (0xa4093822, 0x299f31d0),
+     (0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1)),
+])
+def test_philox_known_answers(ctr, key, expect):
+    """Philox4x32-10 known-answer vectors published with the generator
+    (Salmon et al., SC'11, Random123 distribution)."""
+    assert tuple(int(x) for x in po.philox(ctr, key)) == expect
+
+
+# ---------------------------------------------------------------- background (section 2: n = p/kT, T = 300 K)
+@pytest.mark.parametrize("p,expect", [(20.0, 4.8286e21), (40.0, 9.6573e21), (100.0, 2.41432e22)])
+def test_background_density(p, expect):
+    d = I.config(1, p=p)
+    o = po.Oracle(d, d.species(), I.make_processes())
+    assert abs(o.info()["n_o2"] / expect - 1.0) < 2e-5
+
+
+# ---------------------------------------------------------------- tables, Eq. (1)
+def test_eq1_values():
+    s = I.power_law(np.array([1.0, 4.0]), I.eq1_sigma0_m2(), 0.0, 0.5, 0.0)
+    np.testing.assert_allclose(s, [5.96e-20, 2.98e-20], rtol=1e-12)
+    d = I.config(1)
+    procs = I.make_processes()
+    o = po.Oracle(d, d.species(), procs)
+    ad = [k for k, p in enumerate(procs) if p.kind == "detach"][0]
+    for e, v in ((1.0, 5.96e-20), (4.0, 2.98e-20)):
+        assert abs(o.sigma_at(ad, e) / v - 1) < 1e-4     # log-index interpolation error ~2e-5
+
+
+def test_table_lookup_is_linear_in_log_index():
+    d = I.config(1)
+    t = np.arange(I.TABLE_N, dtype=float)
+    p0 = I.Process("idx", 0, "elastic", "O2", 0.0, I.M_O2, t.copy(), {})
+    p1 = I.Process("thr", 0, "excite", "O2", 1.0, I.M_O2, t.copy(), {})
+    o = po.Oracle(d, species(), [p0, p1])
+    delta = math.log(I.TABLE_EMAX / I.TABLE_EMIN) / (I.TABLE_N - 1)
+    rng = np.random.default_rng(5)
+    for e in np.exp(rng.uniform(math.log(1e-3), math.log(1e3), 50)):
+        assert abs(o.sigma_at(0, e) - math.log(e / I.TABLE_EMIN) / delta) < 1e-9
+    assert o.sigma_at(0, 1e-5) == 0.0              # clamped to the first node
+    assert o.sigma_at(0, 1e5) == I.TABLE_N - 1     # clamped to the last node
+    assert o.sigma_at(1, 0.999) == 0.0             # below threshold
+    assert abs(o.sigma_at(1, 1.001) - math.log(1.001 / I.TABLE_EMIN) / delta) < 1e-9
+
+
+# ---------------------------------------------------------------- Poisson (section 1 source term)
+def test_poisson_uniform_charge_closed_form():
+    ng, L, V, rho0 = 64, 0.01, 100.0, 1e-3
+    dx = L / ng
+    x = np.arange(ng + 1) * dx
+    phi, E = po.poisson(ng, dx, V, np.full(ng + 1, rho0))
+    phi_x = V * (1 - x / L) + rho0 * x * (L - x) / (2 * EPS0)
+    E_x = V / L - rho0 * (L - 2 * x) / (2 * EPS0)
+    assert np.max(np.abs(phi - phi_x)) <= 1e-12 * np.max(np.abs(phi_x))
+    assert np.max(np.abs(E - E_x)) <= 1e-12 * np.max(np.abs(E_x))
+
+
+def test_poisson_node_charge_green_function():
+    ng, L, k, sig = 40, 0.02, 13, 1e-6
+    dx = L / ng
+    x = np.arange(ng + 1) * dx
+    rho = np.zeros(ng + 1)
+    rho[k] = sig / dx
+    phi, E = po.poisson(ng, dx, 0.0, rho)
+    xk = x[k]
+    g = np.where(x <= xk, x * (L - xk) / L, xk * (L - x) / L) * sig / EPS0
+    assert np.max(np.abs(phi - g)) <= 1e-12 * np.max(np.abs(g))
+    slope_l, slope_r = sig / EPS0 * (L - xk) / L, -sig / EPS0 * xk / L
+    np.testing.assert_allclose(E[:k], -slope_l, rtol=1e-10)
+    np.testing.assert_allclose(E[k + 1:], -slope_r, rtol=1e-10)
+    assert abs(E[k] + 0.5 * (slope_l + slope_r)) <= 1e-10 * abs(slope_l)
+
+
+def test_poisson_no_charge_linear():
+    ng, L, V = 32, 0.03, -250.0
+    phi, E = po.poisson(ng, L / ng, V, np.zeros(ng + 1))
+    np.testing.assert_allclose(phi, V * (1 - np.arange(ng + 1) / ng), atol=1e-12 * abs(V))
+    np.testing.assert_allclose(E, V / L, rtol=1e-12)
+
+
+# ---------------------------------------------------------------- deposit
+def test_deposit_cic_invariants():
+    rng = np.random.default_rng(1)
+    ng, n = 32, 5000
+    cell = rng.integers(0, ng, n).astype(np.int32)
+    off = rng.random(n).astype(np.float32)
+    Q = po.deposit_canonical(ng, cell, off)
+    assert Q.sum() == TWO32 * n                                # charge conservation, exact
+    first = int((np.arange(ng + 1, dtype=object) * Q.astype(object)).sum())
+    exact = sum(int(c) * TWO32 for c in cell) + sum(float(o) * TWO32 for o in off)
+    assert abs(first - exact) <= 0.5 * n                        # centre of charge, rounding <= 1/2 unit
+    for o, left in ((0.0, TWO32), (0.5, TWO32 // 2), (0.25, 3 * TWO32 // 4)):
+        q = po.deposit_canonical(4, [2], [o])
+        assert q[2] == left and q[3] == TWO32 - left and q.sum() == TWO32
+
+
+def test_oracle_deposit_matches_canonical():
+    d = I.config(1, n_total=3000)
+    o = po.Oracle(d, d.species(), I.make_processes())
+    o.load_uniform()
+    o.prepare(False)
+    Q = o.hist()
+    for s in range(3):
+        c = o.canonical(s)
+        o2 = po.Oracle(d, d.species(), I.make_processes())
+        np.testing.assert_array_equal(Q[s], po.deposit_canonical(d.ng, c["cell"], c["off"]))
+
+
+# ---------------------------------------------------------------- push (section 2 free flights)
+def test_ballistic_uniform_field():
+    d = I.config(1)
+    E0 = -50.0
+    o = po.Oracle(d, species(16), [], flags=po.F_EXT_FIELD | po.F_NO_COLL, e_ext=(E0, 0.0))
+    rng = np.random.default_rng(2)
+    xi0 = rng.uniform(20, 40, 16)
+    v0 = rng.uniform(-1e5, 1e5, 16)
+    put(o, 0, xi0, v0)
+    empty(o, 1), empty(o, 2)
+    o.prepare(True)
+    n = 200
+    o.step(n)
+    p = o.get_particles(0)
+    a = QE * (-E0) / ME * 1.0                       # q = -e
+    t = n * d.dt
+    dx = d.L / d.ng
+    expect = xi0 + (v0 * t + 0.5 * a * t * t) / dx
+    order = np.argsort(p["id"])
+    np.testing.assert_allclose(p["xi"][order], expect, atol=1e-12 * d.ng)
+    np.testing.assert_allclose(p["vx"][order], v0 + a * (n - 0.5) * d.dt, rtol=1e-12)
+
+
+def test_harmonic_well_shadow_energy():
+    d = I.config(1)
+    w = 0.2 / d.dt
+    E1 = w * w * ME / QE                               # restoring for electrons
+    o = po.Oracle(d, species(4), [], flags=po.F_EXT_FIELD | po.F_NO_COLL, e_ext=(0.0, E1))
+    dx = d.L / d.ng
+    xi0 = np.array([44.0, 60.0, 70.5, 84.0])
+    put(o, 0, xi0, np.array([1e5, -3e5, 2e5, 0.0]))
+    empty(o, 1), empty(o, 2)
+    o.prepare(True)
+    X = lambda p: (p["xi"][np.argsort(p["id"])] - d.ng / 2) * dx
+    prev = X(o.get_particles(0))
+    inv = []
+    for _ in range(3000):
+        o.step(1)
+        p = o.get_particles(0)
+        cur = X(p)
+        v = p["vx"][np.argsort(p["id"])]
+        inv.append(v * v + w * w * prev * cur)
+        prev = cur
+    inv = np.array(inv)
+    assert np.max(np.abs(inv - inv[0]) / np.abs(inv[0])) < 1e-10
+
+
+def test_absorption_tallies():
+    d = I.config(1, diag_every=0)
+    o = po.Oracle(d, species(3), [], flags=po.F_EXT_FIELD | po.F_NO_COLL, e_ext=(0.0, 0.0))
+    dx = d.L / d.ng
+    e_ev = 10.0
+    v = math.sqrt(2 * e_ev * QE / ME)
+    step = v * d.dt / dx
+    put(o, 0, np.array([0.5 * step, d.ng - 0.5 * step, 64.0]), np.array([-v, v, 0.0]))
+    empty(o, 1), empty(o, 2)
+    o.prepare(False)
+    o.step(1)
+    c = o.counters()
+    assert c[po.C_ABS0 + 0] == 1 and c[po.C_ABSL + 0] == 1 and o.count(0) == 1
+    m = o.moments()
+    b = int(math.floor((math.log10(e_ev) + 3) * po.NBIN / 6))
+    assert m["iedf"][0, 0, b] == 1 and m["iedf"][0, 1, b] == 1
+
+
+# ---------------------------------------------------------------- null-collision MCC (section 2)
+def beam_setup(procs, n=20000, e_ev=10.0, L=1000.0, cd_mode="geom", seed=3):
+    d = I.config(1, L=L, diag_every=0)
+    o = po.Oracle(d, species(n), procs, flags=po.F_EXT_FIELD, e_ext=(0.0, 0.0))
+    info = o.info()
+    P = 1 - math.exp(-info["nu_max"][0] * d.dt)
+    rng = np.random.default_rng(seed)
+    cd = rng.geometric(P, n).astype(np.int32) if cd_mode == "geom" else np.ones(n, np.int32)
+    v = math.sqrt(2 * e_ev * QE / ME)
+    put(o, 0, rng.uniform(10, 100, n), np.full(n, v), cd=cd)
+    empty(o, 1), empty(o, 2)
+    o.prepare(False)
+    return d, o, info, P, v
+
+
+def binom_ok(k, n, p, z=4.0):
+    return abs(k - n * p) <= z * math.sqrt(n * p * (1 - p)) + 1
+
+
+def test_collision_count_constant_sigma():
+    sig = 1e-19
+    procs = [I.constant_process("el", 0, "elastic", "O2", sig, target_mass=1e20)]
+    d, o, info, P, v = beam_setup(procs)
+    vmax = math.sqrt(2 * I.TABLE_EMAX * QE / ME)
+    assert abs(info["nu_max"][0] / (info["n_o2"] * sig * vmax) - 1) < 1e-12
+    T = 50
+    o.step(T)
+    c = o.counters()
+    assert binom_ok(c[po.C_CAND + 0], 20000 * T, P)
+    assert binom_ok(c[po.C_EVENT + 0], 20000 * T, P * v / vmax)
+
+
+def test_isotropisation_of_a_beam():
+    procs = [I.constant_process("el", 0, "elastic", "O2", 1e-19, target_mass=1e20)]
+    d, o, info, P, v = beam_setup(procs, n=40000)
+    vmax = math.sqrt(2 * I.TABLE_EMAX * QE / ME)
+    p = P * v / vmax
+    done = 0
+    for n in (3, 8, 20):
+        o.step(n - done)
+        done = n
+        vx = o.get_particles(0)["vx"]
+        N = len(vx)
+        m1, m2 = vx.mean(), (vx * vx).mean()
+        e1 = v * (1 - p) ** n
+        e2 = v * v / 3 + 2 * v * v / 3 * (1 - p) ** n
+        assert abs(m1 - e1) < 4 * vx.std() / math.sqrt(N) + 1e-9 * v
+        assert abs(m2 - e2) < 4 * (vx * vx).std() / math.sqrt(N)
+        np.testing.assert_allclose(np.sqrt(sum(o.get_particles(0)[k] ** 2 for k in ("vx", "vy", "vz"))),
+                                   v, rtol=1e-12)   # infinite target mass: speed unchanged
+
+
+def test_elastic_energy_loss_mean():
+    M = 100 * ME
+    procs = [I.constant_process("el", 0, "elastic", "O2", 1e-19, target_mass=M)]
+    d, o, info, P, v = beam_setup(procs, n=20000, cd_mode="one")
+    o.log_events(True)
+    o.step(1)
+    ev = o.events()
+    hit = set(ev[(ev[:, 3] == 0), 2].tolist())
+    p = o.get_particles(0)
+    e = 0.5 * ME * (p["vx"] ** 2 + p["vy"] ** 2 + p["vz"] ** 2) / QE
+    ratio = np.array([e[k] / 10.0 for k in range(len(e)) if int(p["id"][k]) in hit])
+    assert len(ratio) > 1000
+    assert abs(ratio.mean() - (1 - 2 * ME / M)) < 4 * ratio.std() / math.sqrt(len(ratio))
+    assert ratio.min() >= 1 - 4 * ME / M - 1e-12 and ratio.max() <= 1 + 1e-12
+
+
+def test_process_selection_order():
+    s1, s2 = 3e-20, 1e-20
+    procs = [I.constant_process("el", 0, "elastic", "O2", s1, target_mass=1e20),
+             I.constant_process("ex", 0, "excite", "O2", s2)]
+    d, o, info, P, v = beam_setup(procs, n=40000, cd_mode="one")
+    o.step(1)
+    c = o.counters()
+    vmax = math.sqrt(2 * I.TABLE_EMAX * QE / ME)
+    n = c[po.C_CAND + 0]
+    assert n == 40000
+    assert binom_ok(c[po.C_EVENT + 0], n, s1 / (s1 + s2) * v / vmax)
+    assert binom_ok(c[po.C_EVENT + 1], n, s2 / (s1 + s2) * v / vmax)
+
+
+def test_energy_accounting_excitation_and_ionisation():
+    # excitation: E' = E - E_th exactly
+    procs = [I.constant_process("ex", 0, "excite", "O2", 1e-18, e_th=5.0)]
+    d, o, info, P, v = beam_setup(procs, n=5000, e_ev=20.0, cd_mode="one")
+    o.log_events(True)
+    o.step(1)
+    hit = set(o.events()[:, 2][o.events()[:, 3] == 0].tolist())
+    p = o.get_particles(0)
+    e = 0.5 * ME * (p["vx"] ** 2 + p["vy"] ** 2 + p["vz"] ** 2) / QE
+    col = np.array([int(i) in hit for i in p["id"]])
+    assert col.sum() > 100
+    np.testing.assert_allclose(e[col], 15.0, rtol=1e-12)
+    np.testing.assert_allclose(e[~col], 20.0, rtol=1e-12)
+    # ionisation: primary + secondary = E - E_th, one O2+ per event, ids by parent order
+    procs = [I.constant_process("io", 0, "ionize", "O2", 1e-18, e_th=12.0)]
+    d, o, info, P, v = beam_setup(procs, n=5000, e_ev=40.0, cd_mode="one")
+    o.log_events(True)
+    o.step(1)
+    ev = o.events()
+    parents = np.sort(ev[ev[:, 3] == 0, 2])
+    p = o.get_particles(0)
+    e = dict(zip(p["id"].tolist(), (0.5 * ME * (p["vx"] ** 2 + p["vy"] ** 2 + p["vz"] ** 2) / QE).tolist()))
+    assert len(parents) > 100 and o.count(0) == 5000 + len(parents) and o.count(1) == len(parents)
+    for r, pid in enumerate(parents):
+        assert abs(e[int(pid)] + e[5000 + r] - 28.0) < 1e-12 * 28.0
+    ions = o.get_particles(1)
+    assert sorted(ions["id"].tolist()) == list(range(len(parents)))
+    ke = 0.5 * I.M_O2PLUS * (ions["vx"] ** 2 + ions["vy"] ** 2 + ions["vz"] ** 2)
+    assert abs(ke.mean() / (1.5 * KB * 300) - 1) < 4 * math.sqrt(2 / 3 / len(ke))
+
+
+def test_attachment_removes_electron_adds_negative_ion():
+    procs = [I.constant_process("at", 0, "attach", "O2", 1e-18, e_th=1.0)]
+    d, o, info, P, v = beam_setup(procs, n=5000, e_ev=20.0, cd_mode="one")
+    o.step(1)
+    c = o.counters()
+    k = c[po.C_EVENT + 0]
+    assert k > 100 and o.count(0) == 5000 - k and o.count(2) == k and c[po.C_BORN + 2] == k
+
+
+# ---------------------------------------------------------------- ions
+def ion_setup(procs, npos=0, nneg=0, p=2000.0, c_meta=1.0, seed=7, ti=300 * KB / QE, ng=64, weight=None):
+    d = I.config(1, L=0.025, ng=ng, p=p, c_meta=c_meta, diag_every=0)
+    if weight is not None:
+        d = dataclasses.replace(d, n_plus0=weight * max(npos, 1) / d.L, counts=(1, max(npos, 1), 1))
+    o = po.Oracle(d, species(0, npos, nneg, ti=ti), procs, flags=po.F_EXT_FIELD, e_ext=(0.0, 0.0))
+    return d, o
+
+
+def test_associative_detachment_first_order_decay():
+    """Eq. (1): sigma ~ E^-1/2 makes sigma*g energy independent, so the O- loss
+    per ion step is a constant probability and N(k) = N0 (1-p)^k."""
+    ad = I.Process("ad", 2, "detach", "O2a", 0.0, I.M_O2,
+                   I.power_law_table(I.eq1_sigma0_m2(), 0, 0.5, 0), {})
+    n0 = 20000
+    d, o = ion_setup([ad], nneg=n0)
+    rng = np.random.default_rng(9)
+    vt = math.sqrt(KB * 300 / I.M_OMINUS)
+    put(o, 2, rng.uniform(1, 63, n0), rng.normal(0, vt, n0), rng.normal(0, vt, n0), rng.normal(0, vt, n0))
+    empty(o, 0), empty(o, 1)
+    o.prepare(False)
+    mu = I.M_OMINUS * I.M_O2 / (I.M_OMINUS + I.M_O2)
+    n_o2 = d.p / (KB * 300)
+    nu = d.c_meta * n_o2 * I.eq1_sigma0_m2() * math.sqrt(2 * 1.0 * QE / mu)
+    delta = math.log(I.TABLE_EMAX / I.TABLE_EMIN) / (I.TABLE_N - 1)
+    nu_max_expect = nu * math.exp(delta / 2)
+    dti = d.ksub * d.dt
+    k_ion = 6
+    o.log_events(True)
+    o.step(d.ksub * k_ion)
+    assert abs(o.nu_max(2) / nu_max_expect - 1) < 1e-12
+    p = (1 - math.exp(-nu_max_expect * dti)) * nu / nu_max_expect
+    surv = (1 - p) ** k_ion
+    assert binom_ok(o.count(2), n0, surv)
+    c = o.counters()
+    ne = o.count(0) + c[po.C_ABS0] + c[po.C_ABSL]         # detached electrons, some reach the walls
+    assert ne == n0 - o.count(2)
+    el = o.get_particles(0)
+    ee = 0.5 * ME * (el["vx"] ** 2 + el["vy"] ** 2 + el["vz"] ** 2) / QE
+    assert abs(ee.mean() / (1.5 * KB * 300 / QE) - 1) < 4 * math.sqrt(2 / 3 / len(ee))
+
+
+def test_charge_exchange_thermalises_beam():
+    cx = I.constant_process("cx", 1, "cx", "O2", 5e-19)
+    n0 = 20000
+    d, o = ion_setup([cx], npos=n0, p=200.0)
+    v = math.sqrt(2 * 50.0 * QE / I.M_O2PLUS)
+    rng = np.random.default_rng(11)
+    put(o, 1, rng.uniform(1, 63, n0), np.full(n0, v))
+    empty(o, 0), empty(o, 2)
+    o.prepare(False)
+    o.log_events(True)
+    o.step(1)
+    ev = o.events()
+    hit = set(ev[ev[:, 3] == 0, 2].tolist())
+    p = o.get_particles(1)
+    col = np.array([int(i) in hit for i in p["id"]])
+    ke = 0.5 * I.M_O2 * (p["vx"] ** 2 + p["vy"] ** 2 + p["vz"] ** 2)[col]
+    # after transfer the ion carries a 300 K neutral velocity (mass of O2)
+    assert abs(ke.mean() / (1.5 * KB * 300) - 1) < 4 * math.sqrt(2 / 3 / len(ke))
+    # event probability: P_null * nu(g)/nu_max with g ~ v for a fast beam
+    info = o.info()
+    Pn = 1 - math.exp(-info["nu_max"][1] * d.ksub * d.dt)
+    mu = I.M_O2PLUS * I.M_O2 / (I.M_O2PLUS + I.M_O2)
+    gmax = math.sqrt(2 * I.TABLE_EMAX * QE / mu)
+    assert binom_ok(len(hit), n0, Pn * v / gmax, z=5.0)
+
+
+def test_neutralisation_pairs_one_partner_in_the_same_cell():
+    # sigma ~ E^-1/2 keeps sigma*g flat, so the null-collision bound is tight
+    neut = I.Process("n", 2, "neutralize", "grid+", 0.0, I.M_O2PLUS, I.power_law_table(4e-14, 0, 0.5, 0), {})
+    npos, nneg, ng = 4000, 400, 16
+    d, o = ion_setup([neut], npos=npos, nneg=nneg, ng=ng, weight=6.25e12)
+    rng = np.random.default_rng(13)
+    cpos = rng.integers(0, ng, npos) + 0.5
+    cneg = rng.integers(0, ng, nneg) + 0.5
+    put(o, 1, cpos, np.zeros(npos))
+    put(o, 2, cneg, np.zeros(nneg))
+    empty(o, 0)
+    o.prepare(False)
+    o.log_events(True)
+    before = o.get_particles(1)
+    o.step(1)
+    c = o.counters()
+    ev = o.events()
+    neut_ids = ev[(ev[:, 1] == 2) & (ev[:, 3] == 0), 2]
+    kcell = np.bincount(np.floor(cneg[neut_ids]).astype(int), minlength=ng)
+    assert c[po.C_PAIRED] + c[po.C_DEFICIT] == len(neut_ids) > 10
+    assert o.count(2) == nneg - len(neut_ids)
+    assert o.count(1) == npos - c[po.C_PAIRED]
+    after = set(o.get_particles(1)["id"].tolist())
+    removed = [i for i in before["id"].tolist() if i not in after]
+    key = lambda i: (int(po.philox([i, 0, (1 << 24) | (5 << 16), 0], [d.seed & 0xffffffff, d.seed >> 32])[0]) << 32) | i
+    for j in range(ng):
+        ids_j = [int(i) for i, x in zip(before["id"], before["xi"]) if int(math.floor(x)) == j]
+        want = min(kcell[j], d.pair_rounds, len(ids_j))
+        got = sorted(i for i in removed if int(math.floor(cpos[i])) == j)
+        assert got == sorted(sorted(ids_j, key=key)[:want])
+    # charge: each paired event removes one + and one -
+    Q = o.hist()
+    assert Q[1].sum() == TWO32 * o.count(1) and Q[2].sum() == TWO32 * o.count(2)
+
+
+# ---------------------------------------------------------------- whole discharge
+def neutralising_discharge(n_total=3000):
+    procs = I.make_processes()
+    for p in procs:
+        if p.kind == "neutralize":
+            p.sigma = p.sigma * 3e4        # make ion-ion neutralisation frequent enough to test
+    d = I.config(1, n_total=n_total)
+    return d, procs
+
+
+def test_particle_and_charge_bookkeeping_per_step():
+    d, procs = neutralising_discharge()
+    o = po.Oracle(d, d.species(), procs)
+    o.load_uniform()
+    o.prepare(True)
+    kind = [p.kind for p in procs]
+    ev = lambda c, k: sum(c[po.C_EVENT + i] for i, kk in enumerate(kind) if kk == k)
+    N = [o.count(s) for s in range(3)]
+    c0 = o.counters()
+    seen_neut = 0
+    for _ in range(60):
+        o.step(1)
+        c1 = o.counters()
+        dc = c1 - c0
+        A = [dc[po.C_ABS0 + s] + dc[po.C_ABSL + s] for s in range(3)]
+        I_, Da, Dad, Nn = ev(dc, "ionize"), ev(dc, "attach"), ev(dc, "detach"), ev(dc, "neutralize")
+        N1 = [o.count(s) for s in range(3)]
+        assert N1[0] == N[0] - A[0] + I_ - Da + Dad
+        assert N1[1] == N[1] - A[1] + I_ - dc[po.C_PAIRED]
+        assert N1[2] == N[2] - A[2] + Da - Nn - Dad
+        assert dc[po.C_PAIRED] + dc[po.C_DEFICIT] == Nn
+        Q = o.hist()
+        for s in range(3):
+            assert Q[s].sum() == TWO32 * N1[s]
+        seen_neut += Nn
+        N, c0 = N1, c1
+    assert seen_neut > 0 and ev(c0, "ionize") > 0 and ev(c0, "detach") >= 0
+
+
+def test_loading_statistics():
+    d = I.config(1)
+    o = po.Oracle(d, d.species(), I.make_processes())
+    o.load_uniform()
+    info = o.info()
+    from scipy import stats
+    for s, sp in enumerate(d.species()):
+        p = o.get_particles(s)
+        assert len(p["xi"]) == sp.count
+        assert stats.kstest(p["xi"] / d.ng, "uniform").pvalue > 1e-4
+        ke = 0.5 * sp.mass * (p["vx"] ** 2 + p["vy"] ** 2 + p["vz"] ** 2) / QE
+        assert abs(ke.mean() - 1.5 * sp.t0_ev) < 4 * math.sqrt(1.5) * sp.t0_ev / math.sqrt(sp.count)
+        for k in ("vx", "vy", "vz"):
+            assert abs(p[k].mean()) < 4 * p[k].std() / math.sqrt(sp.count)
+    cd = o.get_particles(0)["cd"]
+    P = 1 - math.exp(-info["nu_max"][0] * d.dt)
+    assert abs(cd.mean() - 1 / P) < 4 * math.sqrt(1 - P) / P / math.sqrt(len(cd))
+    assert sorted(o.get_particles(0)["id"].tolist()) == list(range(d.species()[0].count))
+
+
+def test_energy_moments_and_density_sums():
+    d = I.config(1, diag_every=1)
+    o = po.Oracle(d, species(3), [], flags=po.F_EXT_FIELD | po.F_NO_COLL)
+    es = np.array([1.0, 2.0, 3.0])
+    put(o, 0, np.full(3, 5.5), np.sqrt(2 * es * QE / ME) * 1e-30 + 0.0)
+    put(o, 0, np.full(3, 5.5), np.zeros(3), np.sqrt(2 * es * QE / ME))   # moving along y: stays in cell 5
+    empty(o, 1), empty(o, 2)
+    o.prepare(False)
+    Q0 = o.hist().astype(float)
+    o.step(1)
+    m = o.moments()
+    assert m["nacc"] == 1 and m["ndiag"] == 1
+    np.testing.assert_array_equal(m["sumQ"], Q0)
+    assert m["ecnt"][0, 5] == 3 and abs(m["esum"][0, 5] - 6 * 2 ** 20) <= 2
+    for e in es:
+        assert m["edf"][0, int(math.floor((math.log10(e) + 3) * po.NBIN / 6))] == 1
+
+
+def test_resume_is_bitwise():
+    d, procs = neutralising_discharge()
+    a = po.Oracle(d, d.species(), procs)
+    a.load_uniform()
+    a.prepare(True)
+    b = po.Oracle(d, d.species(), procs)
+    b.load_uniform()
+    b.prepare(True)
+    a.step(47)
+    b.step(21)
+    c = po.Oracle(d, d.species(), procs)
+    for s in range(3):
+        c.set_particles64(s, b.get_particles(s), b.next_id(s))
+    c.set_step(b.step_index)
+    c.prepare(False)
+    c.step(26)
+    for s in range(3):
+        pa, pc = a.get_particles(s), c.get_particles(s)
+        oa, oc = np.argsort(pa["id"]), np.argsort(pc["id"])
+        for k in ("xi", "vx", "vy", "vz", "id", "cd"):
+            np.testing.assert_array_equal(pa[k][oa], pc[k][oc])
