@@ -1,0 +1,138 @@
+"""Throughput of the 1D3V oxygen PIC-MCC step on one MI355X.
+
+Workload: the large single discharge (4096 cells, L = 4 cm, U = 500 V,
+p = 100 Pa, 8e6 e + 2.4e7 O2+ + 1.6e7 O-, 2000 steps per rf cycle, ions every
+20 steps, cell sort every 20 steps).  One bench "step" is one rf cycle: 2000
+electron steps with 100 ion steps, field solves, MCC, deposits, sorts and
+moments.  Inputs (seeded synthetic tables, uniform loading) are resident on the
+GPU before the timed region starts.
+
+Prints one JSON line.  Roofline of the dominant kernel (electron
+push+MCC+deposit): algorithmic bytes per launch / mean launch duration from
+HIP events on the handle's stream.  cpu_baseline: the FP64 oracle on a bounded
+sample of the same workload (1/8 of the particles, 40 steps) on the host.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+BYTES_PUSH = 24          # read + write cell word, offset, vx
+BYTES_CAND = 20          # read id, vy, vz; write vy, vz at a free-flight end
+BYTES_PRODUCT = 24       # one new particle record
+HBM_PEAK_GBS = 8000.0    # MI355X HBM3E
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(d, procs):
+    """FP64 oracle on 1/8 of the particles of the same discharge, 40 steps."""
+    import dataclasses
+    from oracle import pyoracle as po
+    counts = tuple(c // 8 for c in d.species_counts())
+    ds = dataclasses.replace(d, counts=counts)
+    o = po.Oracle(ds, ds.species(), procs)
+    o.load_uniform()
+    o.prepare(True)
+    c0 = o.counters()
+    steps = 40
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    pushes = int((o.counters() - c0)[0:3].sum())
+    return {"value": pushes / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"same discharge with 1/8 of the superparticles ({sum(counts)}), {steps} steps "
+                      f"incl. {steps // d.ksub} ion steps, single thread, {pushes} pushes in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50, help="timed rf cycles")
+    ap.add_argument("--warmup", type=int, default=5, help="untimed rf cycles")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--grid", type=int, default=0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs one discharge on one GPU; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is described in DESIGN.md, not implemented)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_0705_0497_amd import inputs as I
+    from paper_0705_0497_amd.binding import Discharge, C_PUSH, C_CAND, C_REDRAW, C_BORN
+
+    torch.cuda.set_device(0)
+    d = I.config(3)
+    procs = I.make_processes()
+    log(f"bench: loading {d.name} ({sum(d.species_counts())} superparticles, {d.ng} cells)")
+    g = Discharge(d, procs, block=args.block, grid=args.grid)
+    g.load_uniform()
+    g.sync()
+    spc = d.steps_per_cycle
+    for c in range(args.warmup):
+        g.step(spc)
+        g.sync()
+        log(f"bench: warmup cycle {c + 1}/{args.warmup} done")
+    c0 = g.counters()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ms_push = 0.0
+    for c in range(args.steps):
+        mp, mt, _ = g.step_timed(spc)
+        ms_push += mp
+        if (c + 1) % 10 == 0 or c + 1 == args.steps:
+            log(f"bench: timed cycle {c + 1}/{args.steps}")
+    g.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    dc = g.counters() - c0
+    pushes = int(dc[C_PUSH:C_PUSH + 3].sum())
+    value = pushes / elapsed
+    launches = args.steps * spc
+    alg_bytes = (BYTES_PUSH * int(dc[C_PUSH]) + BYTES_CAND * int(dc[C_CAND] + dc[C_REDRAW])
+                 + BYTES_PRODUCT * int(dc[C_BORN:C_BORN + 3].sum()))
+    per_launch = alg_bytes / launches
+    mean_ms = ms_push / launches
+    achieved = per_launch / (mean_ms * 1e-3) / 1e9
+    counts = [g.count(s) for s in range(3)]
+    out = {
+        "metric": "particle-steps/s (push+deposit+MCC); rf cycles to steady state, warm vs cold",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "4096-cell O2 CCP, L=4 cm, U=500 V, p=100 Pa, 8e6 e + 2.4e7 O2+ + 1.6e7 O-",
+                   "step": "one rf cycle = 2000 electron steps, ions every 20, sort every 20",
+                   "cells": d.ng, "superparticles_loaded": int(sum(d.species_counts())),
+                   "superparticles_end": counts, "electron_pushes": int(dc[C_PUSH]),
+                   "ion_pushes": int(dc[C_PUSH + 1] + dc[C_PUSH + 2]),
+                   "electron_candidates": int(dc[C_CAND]), "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "k_push<512,0> electron push+MCC+deposit",
+                     "bytes_per_launch": per_launch, "mean_launch_ms": mean_ms},
+    }
+    if not args.no_cpu_baseline:
+        log("bench: timing the FP64 oracle on the host (bounded sample)")
+        out["cpu_baseline"] = cpu_baseline(d, procs)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

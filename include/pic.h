@@ -1,0 +1,234 @@
+/*
+ * pic.h - C ABI of the MI355X (gfx950) PIC-MCC library for one-dimensional,
+ * three-velocity (1D3V) capacitively coupled rf discharges in oxygen.
+ *
+ * Method: Bronold, Matyash, Tskhakaya, Schneider, Fehske, "Particle-based
+ * modeling of oxygen discharges", ICPIG 2007.
+ *   - Section 1: the discharge is the Boltzmann-Poisson system solved with
+ *     pseudo-particles; collisions enter through cross sections and the
+ *     chemistry reaches the field through the Poisson source term.
+ *   - Section 2: gap 0 <= x <= L, velocities (vx, vy, vz); the electrode at
+ *     x = 0 is driven at U sin(2 pi f t), the one at x = L is grounded; both
+ *     absorb everything that reaches them (no secondary emission); the O2
+ *     reservoir has density p / kT at T = 300 K; free flights alternate with
+ *     collisions whose timing and channel follow from the cross sections;
+ *     species e, O-, O2+; channels of Table 1; Eq. (1) for associative
+ *     detachment with n(O2(a)) = C n(O2).
+ *
+ * Conventions shared by every call:
+ *   - Species index 0 = electrons, 1 = O2+, 2 = O-.
+ *   - Return value: 0 (PIC_OK) on success, a negative PIC_E* code on error.
+ *     No call throws.  pic_last_error() gives a message for the last error.
+ *   - Device memory: the library allocates none.  The caller allocates ONE
+ *     device buffer of the size pic_query() reports, passes it to
+ *     pic_create(), and keeps it alive until pic_destroy().  Host pointers
+ *     passed to calls are read or written before the call returns.
+ *   - Streams: all device work of a handle is enqueued on the hipStream_t
+ *     given to pic_create().  pic_step() does not synchronise; calls that
+ *     return data to the host synchronise that stream.  A handle is not
+ *     thread-safe; different handles on different streams are independent.
+ *   - Device-side errors (storage full, id overflow, NaN) are sticky flags
+ *     reported by the next synchronising call.
+ */
+#ifndef PIC_H
+#define PIC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIC_OK 0
+#define PIC_EINVAL (-1)        /* invalid argument or configuration */
+#define PIC_ECAPACITY (-2)     /* particle storage or per-step product buffer full */
+#define PIC_EIDOVERFLOW (-3)   /* 32-bit particle ids exhausted */
+#define PIC_ENAN (-5)          /* non-finite particle coordinate */
+#define PIC_EHIP (-6)          /* HIP runtime error */
+#define PIC_ENODEVICE (-7)     /* no usable gfx950 device */
+
+/* process kinds (Table 1 channels handled by the library) */
+#define PIC_ELASTIC 0      /* e + O2 elastic (7) */
+#define PIC_EXCITE 1       /* e + O2 energy loss (10)-(15): E -> E - E_th */
+#define PIC_IONIZE 2       /* e + O2 -> 2e + O2+ (21) */
+#define PIC_ATTACH 3       /* e + O2 -> O + O- (18) */
+#define PIC_CX 4           /* O2+ + O2 charge exchange (9) */
+#define PIC_NEUTRALIZE 5   /* O- + O2+ -> O + O2 (17), partner density from the grid */
+#define PIC_DETACH 6       /* O- + O2(a) -> O3 + e (20) */
+
+/* collision partners */
+#define PIC_T_O2 0         /* O2 background, n = p / kT */
+#define PIC_T_O2A 1        /* metastable O2(a), n = C p / kT */
+#define PIC_T_GRIDPOS 2    /* O2+ density of the simulation grid */
+
+/* configuration flags (test hooks) */
+#define PIC_F_EXT_FIELD 1  /* E(x) = e_ext0 + e_ext1 (x - L/2) replaces the Poisson field */
+#define PIC_F_NO_COLL 2    /* collisions off */
+
+/* periodic re-ordering of the particle store (both drop absorbed and removed particles) */
+#define PIC_SORT_CELL 0    /* counting sort by cell */
+#define PIC_SORT_COMPACT 1 /* order-preserving compaction */
+
+#define PIC_NBIN 256       /* log energy bins from 1e-3 to 1e3 eV */
+#define PIC_NCOUNT 40      /* counters, layout below */
+
+/* counter layout (int64): index + species or + process */
+#define PIC_C_PUSH 0       /* +s particles pushed */
+#define PIC_C_CAND 3       /* +s collision candidates */
+#define PIC_C_NULL 6       /* +s null collisions */
+#define PIC_C_ABS0 9       /* +s absorbed at x = 0 */
+#define PIC_C_ABSL 12      /* +s absorbed at x = L */
+#define PIC_C_BORN 15      /* +s products born */
+#define PIC_C_EVENT 18     /* +p real collisions of process p (p < 16) */
+#define PIC_C_PAIRED 34    /* O2+ removed as neutralisation partners */
+#define PIC_C_DEFICIT 35   /* neutralisations that found no partner */
+#define PIC_C_CLAMP 36     /* energies clamped into the table range */
+#define PIC_C_REDRAW 37    /* capped free flights redrawn */
+
+typedef struct pic_config {
+  double L;                /* gap [m], > 0 */
+  int32_t ng;              /* cells, 2 .. 8192; nodes are ng + 1 */
+  double U;                /* rf amplitude [V] at x = 0 */
+  double f;                /* rf frequency [Hz] */
+  double p;                /* O2 pressure [Pa] */
+  double t_gas;            /* gas temperature [K] (300 in the paper) */
+  int32_t steps_per_cycle; /* electron steps per rf period; dt = 1 / (f steps_per_cycle) */
+  int32_t ksub;            /* ions move every ksub steps with dt_i = ksub dt */
+  double c_meta;           /* C in n(O2(a)) = C n(O2), 0 <= C < 1 */
+  uint64_t seed;           /* key of the counter-based random streams */
+  double weight;           /* physical particles per superparticle per m^2 of electrode */
+  int32_t diag_every;      /* energy moments sampled every diag_every steps (0 = never) */
+  int32_t pair_rounds;     /* at most this many O2+ partners removed per cell per ion step */
+  int32_t sort_every;      /* particles re-ordered by cell every sort_every steps (0 = never) */
+  int32_t flags;           /* PIC_F_* */
+  double e_ext0, e_ext1;   /* field of PIC_F_EXT_FIELD [V/m], [V/m^2] */
+  double table_emin, table_emax; /* energy range of the tables [eV] */
+  int32_t table_n;         /* points per table, log-spaced, 2 .. 4096 */
+  int32_t max_products;    /* products per species per step, 1 .. 2^24 */
+  int32_t event_capacity;  /* records of the collision event log (0 = off) */
+  int32_t block;           /* threads per block of the particle kernels (0 = default) */
+  int32_t grid;            /* blocks of the particle kernels (0 = default), <= 2048 */
+  int32_t sort_kind;       /* PIC_SORT_CELL or PIC_SORT_COMPACT, applied every sort_every steps */
+} pic_config;
+
+typedef struct pic_species {
+  double charge;           /* in units of e: -1 (e), +1 (O2+), -1 (O-) */
+  double mass;             /* kg */
+  double t0_ev;            /* Maxwellian loading temperature [eV] */
+  int64_t count;           /* superparticles loaded by pic_load_uniform */
+  int64_t capacity;        /* slots reserved in device memory (>= count) */
+} pic_species;
+
+typedef struct pic_process {
+  int32_t species;         /* projectile species index */
+  int32_t kind;            /* PIC_ELASTIC .. PIC_DETACH */
+  int32_t target;          /* PIC_T_* */
+  double e_th;             /* threshold [eV]; sigma = 0 below it */
+  double target_mass;      /* partner mass [kg] */
+  const double *sigma;     /* host array of table_n cross sections [m^2] on the log grid
+                              E_k = emin (emax/emin)^(k/(table_n-1)); copied by pic_create */
+} pic_process;
+
+/* Cycle accumulators returned by pic_moments (host arrays owned by the caller;
+   any pointer may be NULL to skip that output). */
+typedef struct pic_moments_out {
+  double *sum_q;           /* [3][ng+1] sum over steps of the node charge (2^-32 superparticle units) */
+  double *sum_phi;         /* [ng+1] sum over steps of the potential [V] */
+  int64_t *esum;           /* [3][ng] sum of kinetic energies per cell, 2^-20 eV units */
+  int64_t *ecnt;           /* [3][ng] particles counted per cell */
+  int64_t *edf;            /* [3][PIC_NBIN] energy distribution counts */
+  int64_t *iedf;           /* [3][2][PIC_NBIN] energies of particles absorbed at x=0 / x=L */
+  int64_t nacc;            /* steps accumulated in sum_q / sum_phi */
+  int64_t ndiag;           /* diagnostic samples in esum / ecnt / edf */
+} pic_moments_out;
+
+typedef struct pic_handle pic_handle;
+
+/* Library version (major * 10000 + minor * 100 + patch). */
+int32_t pic_version(void);
+
+/* Validates the configuration and reports the device bytes pic_create needs.
+   Pure host call. */
+int pic_query(const pic_config *cfg, const pic_species *sp /* [3] */, const pic_process *pr,
+              int32_t nproc, uint64_t *workspace_bytes);
+
+/* Creates a discharge on the current HIP device.  `workspace` is caller-owned
+   device memory of at least pic_query() bytes; `stream` is a hipStream_t (NULL =
+   default stream).  Tables are copied; particles are empty until
+   pic_load_uniform or pic_set_particles. */
+int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *pr, int32_t nproc,
+               void *workspace, uint64_t workspace_bytes, void *stream, pic_handle **out);
+
+int pic_destroy(pic_handle *h);
+
+/* Uniform loading (section 2 geometry): species s gets sp[s].count particles
+   with ids 0..count-1 on the 2^24-point lattice of [0, L) and Maxwellian
+   velocities at t0_ev, then pic_prepare(h, 1). */
+int pic_load_uniform(pic_handle *h);
+
+/* Canonical particle record exchanged with the host (arrays of n):
+   cell in [0, ng), off in [0, 1) (x = (cell + off) L / ng), vx, vy, vz [m/s],
+   id, and for electrons the countdown word cd = steps left in the current free
+   flight (1..32767) | 0x8000 when the flight was capped.  set replaces the
+   species' particles; next_id is the id the next product receives. */
+int pic_set_particles(pic_handle *h, int32_t s, int64_t n, const int32_t *cell, const float *off,
+                      const float *vx, const float *vy, const float *vz, const uint32_t *id,
+                      const int32_t *cd, uint32_t next_id);
+
+/* Number of live particles of species s (synchronises). */
+int pic_count(pic_handle *h, int32_t s, int64_t *n);
+
+/* Copies the live particles of s into host arrays of at least *n entries;
+   *n returns the count.  Order is unspecified (match by id). */
+int pic_get_particles(pic_handle *h, int32_t s, int64_t *n, int32_t *cell, float *off, float *vx,
+                      float *vy, float *vz, uint32_t *id, int32_t *cd, uint32_t *next_id);
+
+/* Rebuilds the charge histograms from the particles; with shift != 0 also
+   solves the field at the current step and moves every velocity back by half
+   its step (leapfrog start). */
+int pic_prepare(pic_handle *h, int32_t shift);
+
+/* Sets / reads the index n of the next step (t_n = n dt). */
+int pic_set_step(pic_handle *h, int64_t step);
+int pic_get_step(pic_handle *h, int64_t *step);
+
+/* Advances n_steps electron steps (ions every ksub-th): field solve, push,
+   null-collision MCC, products, charge deposit, moments.  Asynchronous. */
+int pic_step(pic_handle *h, int64_t n_steps);
+
+/* Waits for the stream and reports sticky device errors. */
+int pic_sync(pic_handle *h);
+
+/* Copies the accumulators to the host (synchronises); reset != 0 clears them. */
+int pic_moments(pic_handle *h, pic_moments_out *out, int32_t reset);
+
+/* Charge histograms [3][ng+1] (2^-32 superparticle units), potential [ng+1]
+   [V] and node field [ng+1] [V/m] of the last field solve, counters
+   [PIC_NCOUNT].  All synchronise. */
+int pic_get_hist(pic_handle *h, int64_t *q);
+int pic_get_field(pic_handle *h, double *phi, float *e);
+int pic_get_counters(pic_handle *h, int64_t *out);
+
+/* Collision event log (config event_capacity > 0): records of 4 int64
+   {step, species, id, code}; code >= 0 process index, -1 null collision,
+   -2 capped flight redrawn, -3 absorbed (electrode in the id's record aux is
+   not kept).  Returns the number of events since the last clear in *n; copies
+   min(*n, max) records.  clear != 0 empties the log. */
+int pic_get_events(pic_handle *h, int64_t max, int64_t *rec, int64_t *n, int32_t clear);
+
+/* Collision-frequency bound used by the null-collision test of species s [1/s]
+   (for O- the value of the last ion step). */
+int pic_nu_max(pic_handle *h, int32_t s, double *nu);
+
+/* Timing of the kernels of the next n_steps steps (synchronises): total device
+   time of the electron push kernel and of everything else, measured with HIP
+   events on the handle's stream, plus the launches of the push kernel. */
+int pic_step_timed(pic_handle *h, int64_t n_steps, double *ms_push_e, double *ms_total,
+                   int64_t *push_launches);
+
+const char *pic_strerror(int code);
+const char *pic_last_error(const pic_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -24,6 +24,7 @@ typedef struct {
   uint32_t *id;
   int32_t *cd;                 /* electrons: steps left in the free flight */
   uint8_t *capped, *alive;
+  uint8_t *pband;              /* product whose own first draw fell in the band */
   uint64_t *pkey;              /* parent key of a product born this step */
   uint32_t next_id;
 } orc_store;
@@ -191,6 +192,7 @@ static void store_reserve(orc_store *a, int64_t need) {
   a->cd = realloc(a->cd, cap * sizeof(int32_t));
   a->capped = realloc(a->capped, cap);
   a->alive = realloc(a->alive, cap);
+  a->pband = realloc(a->pband, cap);
   a->pkey = realloc(a->pkey, cap * sizeof(uint64_t));
   a->cap = cap;
 }
@@ -198,7 +200,7 @@ static void store_reserve(orc_store *a, int64_t need) {
 static int64_t store_push(orc_store *a) {
   store_reserve(a, a->n + 1);
   int64_t i = a->n++;
-  a->alive[i] = 1; a->capped[i] = 0; a->cd[i] = 0; a->id[i] = 0; a->pkey[i] = 0;
+  a->alive[i] = 1; a->capped[i] = 0; a->cd[i] = 0; a->id[i] = 0; a->pkey[i] = 0; a->pband[i] = 0;
   return i;
 }
 
@@ -247,7 +249,7 @@ void orc_destroy(orc_sim *S) {
   for (int s = 0; s < ORC_NSP; ++s) {
     orc_store *a = &S->st[s];
     free(a->xi); free(a->vx); free(a->vy); free(a->vz); free(a->id); free(a->cd);
-    free(a->capped); free(a->alive); free(a->pkey);
+    free(a->capped); free(a->alive); free(a->pkey); free(a->pband);
   }
   free(S->sigma); free(S->Q); free(S->phi); free(S->E); free(S->sumQ); free(S->sumphi);
   free(S->esum); free(S->ecnt); free(S->edf); free(S->iedf); free(S->kcell); free(S->ev);
@@ -261,6 +263,8 @@ void orc_destroy(orc_sim *S) {
 static void new_flight(const orc_sim *S, uint32_t x, int32_t *cd, uint8_t *capped, int64_t *band) {
   double nd = S->numax[ORC_E] * S->dt;
   double tau = nd > 0.0 ? -log(unif(x)) / nd : INFINITY;
+  /* decisions within 1e-6 (relative) of an integer step or of the cap lie in the band */
+  if (band && isfinite(tau) && fabs(tau - (double)ORC_CD_MAX) < 1e-6 * tau) *band |= 2;
   if (tau >= (double)ORC_CD_MAX) { *cd = ORC_CD_MAX; *capped = 1; return; }
   double fl = floor(tau);
   if (band && (tau - fl < 1e-6 * fmax(1.0, tau) || fl + 1.0 - tau < 1e-6 * fmax(1.0, tau))) *band |= 2;
@@ -527,7 +531,9 @@ static void collide_electron(orc_sim *S, int64_t i) {
     double v2m = sqrt(2.0 * r * er * Q_E / me);
     v[0] = v2m * d2[0]; v[1] = v2m * d2[1]; v[2] = v2m * d2[2];
     int64_t k = add_product(S, ORC_E, a->xi[i], v, ((uint64_t)ORC_E << 32) | id);
-    new_flight(S, p0[3], &a->cd[k], &a->capped[k], NULL);
+    int64_t pb = 0;
+    new_flight(S, p0[3], &a->cd[k], &a->capped[k], &pb);
+    a->pband[k] = pb != 0;
     /* new O2+ from the 300 K reservoir */
     maxwellian(S, S->sp[ORC_POS].mass, p1, v);
     add_product(S, ORC_POS, a->xi[i], v, ((uint64_t)ORC_E << 32) | id);
@@ -600,7 +606,9 @@ static void collide_ion(orc_sim *S, int s, int64_t i, double dts) {
     double vm = sqrt(2.0 * erel_chosen * Q_E / S->sp[ORC_E].mass);
     v[0] = vm * d[0]; v[1] = vm * d[1]; v[2] = vm * d[2];
     int64_t k = add_product(S, ORC_E, a->xi[i], v, ((uint64_t)s << 32) | id);
-    new_flight(S, p0[3], &S->st[ORC_E].cd[k], &S->st[ORC_E].capped[k], NULL);
+    int64_t pb = 0;
+    new_flight(S, p0[3], &S->st[ORC_E].cd[k], &S->st[ORC_E].capped[k], &pb);
+    S->st[ORC_E].pband[k] = pb != 0;
     a->alive[i] = 0;
   }
 }
@@ -689,6 +697,7 @@ static void assign_ids(orc_sim *S) {
       /* rank of this product's key among the sorted keys (keys are unique) */
       uint64_t *hit = bsearch(&a->pkey[b + k], keys, nb, sizeof(uint64_t), cmp_u64);
       a->id[b + k] = a->next_id + (uint32_t)(hit - keys);
+      if (a->pband[b + k]) log_event(S, s, a->id[b + k], -5, 2, 0);   /* product's own draw in the band */
     }
     a->next_id += (uint32_t)nb;
     free(keys);
@@ -704,7 +713,7 @@ static void compact(orc_sim *S) {
       if (k != i) {
         a->xi[k] = a->xi[i]; a->vx[k] = a->vx[i]; a->vy[k] = a->vy[i]; a->vz[k] = a->vz[i];
         a->id[k] = a->id[i]; a->cd[k] = a->cd[i]; a->capped[k] = a->capped[i];
-        a->alive[k] = 1; a->pkey[k] = a->pkey[i];
+        a->alive[k] = 1; a->pkey[k] = a->pkey[i]; a->pband[k] = 0;
       }
       ++k;
     }
@@ -782,6 +791,11 @@ void orc_step(orc_sim *S, int64_t nsteps) {
 void orc_get_hist(const orc_sim *S, int64_t *Q) {
   memcpy(Q, S->Q, sizeof(int64_t) * ORC_NSP * (S->c.ng + 1));
 }
+/* test hook: histograms of a larger state, for pushing a sample of its particles */
+void orc_set_hist(orc_sim *S, const int64_t *Q) {
+  memcpy(S->Q, Q, sizeof(int64_t) * ORC_NSP * (S->c.ng + 1));
+}
+
 void orc_get_field(const orc_sim *S, double *phi, double *E) {
   if (phi) memcpy(phi, S->phi, sizeof(double) * (S->c.ng + 1));
   if (E) memcpy(E, S->E, sizeof(double) * (S->c.ng + 1));

@@ -116,6 +116,7 @@ void orc_prepare(orc_sim *S, int32_t shift);
 void orc_step(orc_sim *S, int64_t nsteps);
 
 void orc_get_hist(const orc_sim *S, int64_t *Q);
+void orc_set_hist(orc_sim *S, const int64_t *Q);   /* test hook */
 void orc_get_field(const orc_sim *S, double *phi, double *E);
 void orc_get_counters(const orc_sim *S, int64_t *out);
 double orc_nu_max(const orc_sim *S, int32_t s);

@@ -84,6 +84,7 @@ def lib():
         L.orc_step.argtypes = [vp, i64]
         L.orc_get_hist.argtypes = [vp, vp]
         L.orc_get_field.argtypes = [vp, vp, vp]
+        L.orc_set_hist.argtypes = [vp, vp]
         L.orc_get_counters.argtypes = [vp, vp]
         L.orc_nu_max.restype = dbl
         L.orc_nu_max.argtypes = [vp, i32]
@@ -224,6 +225,10 @@ class Oracle:
         Q = np.zeros((3, self.ng + 1), dtype=np.int64)
         lib().orc_get_hist(self.h, _p(Q))
         return Q
+
+    def set_hist(self, Q):
+        Q = np.ascontiguousarray(Q, dtype=np.int64)
+        lib().orc_set_hist(self.h, _p(Q))
 
     def field(self):
         phi = np.zeros(self.ng + 1)

@@ -1,0 +1,358 @@
+"""Thin ctypes binding of include/pic.h.
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+libpicmcc.so.  PyTorch supplies the device workspace and the stream.  There is
+no fallback: if the library is missing or no gfx950 device is present, calls
+raise.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpicmcc.so")
+
+PIC_OK, PIC_EINVAL, PIC_ECAPACITY, PIC_EIDOVERFLOW, PIC_ENAN, PIC_EHIP, PIC_ENODEVICE = 0, -1, -2, -3, -5, -6, -7
+KIND = {"elastic": 0, "excite": 1, "ionize": 2, "attach": 3, "cx": 4, "neutralize": 5, "detach": 6}
+TARGET = {"O2": 0, "O2a": 1, "grid+": 2}
+F_EXT_FIELD, F_NO_COLL = 1, 2
+NBIN, NCOUNT = 256, 40
+C_PUSH, C_CAND, C_NULL, C_ABS0, C_ABSL, C_BORN, C_EVENT = 0, 3, 6, 9, 12, 15, 18
+C_PAIRED, C_DEFICIT, C_CLAMP, C_REDRAW = 34, 35, 36, 37
+
+EXPORTS = ("pic_version", "pic_query", "pic_create", "pic_destroy", "pic_load_uniform", "pic_set_particles",
+           "pic_count", "pic_get_particles", "pic_prepare", "pic_set_step", "pic_get_step", "pic_step",
+           "pic_sync", "pic_moments", "pic_get_hist", "pic_get_field", "pic_get_counters", "pic_get_events",
+           "pic_nu_max", "pic_step_timed", "pic_strerror", "pic_last_error")
+
+
+class PicError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class pic_config(C.Structure):
+    _fields_ = [("L", C.c_double), ("ng", C.c_int32), ("U", C.c_double), ("f", C.c_double), ("p", C.c_double),
+                ("t_gas", C.c_double), ("steps_per_cycle", C.c_int32), ("ksub", C.c_int32), ("c_meta", C.c_double),
+                ("seed", C.c_uint64), ("weight", C.c_double), ("diag_every", C.c_int32),
+                ("pair_rounds", C.c_int32), ("sort_every", C.c_int32), ("flags", C.c_int32),
+                ("e_ext0", C.c_double), ("e_ext1", C.c_double), ("table_emin", C.c_double),
+                ("table_emax", C.c_double), ("table_n", C.c_int32), ("max_products", C.c_int32),
+                ("event_capacity", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
+                ("sort_kind", C.c_int32)]
+
+
+class pic_species(C.Structure):
+    _fields_ = [("charge", C.c_double), ("mass", C.c_double), ("t0_ev", C.c_double), ("count", C.c_int64),
+                ("capacity", C.c_int64)]
+
+
+class pic_process(C.Structure):
+    _fields_ = [("species", C.c_int32), ("kind", C.c_int32), ("target", C.c_int32), ("e_th", C.c_double),
+                ("target_mass", C.c_double), ("sigma", C.POINTER(C.c_double))]
+
+
+class pic_moments_out(C.Structure):
+    _fields_ = [("sum_q", C.c_void_p), ("sum_phi", C.c_void_p), ("esum", C.c_void_p), ("ecnt", C.c_void_p),
+                ("edf", C.c_void_p), ("iedf", C.c_void_p), ("nacc", C.c_int64), ("ndiag", C.c_int64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libpicmcc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} missing (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u32, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_uint32, C.c_double
+        P = C.POINTER
+        L.pic_version.restype = i32
+        L.pic_query.argtypes = [P(pic_config), P(pic_species), P(pic_process), i32, P(C.c_uint64)]
+        L.pic_create.argtypes = [P(pic_config), P(pic_species), P(pic_process), i32, vp, C.c_uint64, vp, P(vp)]
+        L.pic_destroy.argtypes = [vp]
+        L.pic_load_uniform.argtypes = [vp]
+        L.pic_set_particles.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, u32]
+        L.pic_count.argtypes = [vp, i32, P(i64)]
+        L.pic_get_particles.argtypes = [vp, i32, P(i64), vp, vp, vp, vp, vp, vp, vp, P(u32)]
+        L.pic_prepare.argtypes = [vp, i32]
+        L.pic_set_step.argtypes = [vp, i64]
+        L.pic_get_step.argtypes = [vp, P(i64)]
+        L.pic_step.argtypes = [vp, i64]
+        L.pic_sync.argtypes = [vp]
+        L.pic_moments.argtypes = [vp, P(pic_moments_out), i32]
+        L.pic_get_hist.argtypes = [vp, vp]
+        L.pic_get_field.argtypes = [vp, vp, vp]
+        L.pic_get_counters.argtypes = [vp, vp]
+        L.pic_get_events.argtypes = [vp, i64, vp, P(i64), i32]
+        L.pic_nu_max.argtypes = [vp, i32, P(dbl)]
+        L.pic_step_timed.argtypes = [vp, i64, P(dbl), P(dbl), P(i64)]
+        L.pic_strerror.restype = C.c_char_p
+        L.pic_strerror.argtypes = [i32]
+        L.pic_last_error.restype = C.c_char_p
+        L.pic_last_error.argtypes = [vp]
+        _lib = L
+    return _lib
+
+
+def _check(code, h=None):
+    if code != PIC_OK:
+        msg = lib().pic_last_error(h).decode() or lib().pic_strerror(code).decode()
+        raise PicError(code, msg)
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+# ---------------------------------------------------------------- struct builders
+SORT_CELL, SORT_COMPACT = 0, 1
+
+
+def make_config(d, flags=0, e_ext=(0.0, 0.0), seed=None, max_products=None, event_capacity=0, block=0, grid=0,
+                sort_every=None, diag_every=None, table=(1e-3, 1e3, 512), sort_kind=None):
+    if max_products is None:
+        max_products = int(min(1 << 24, max(4096, sum(d.species_counts()) // 16)))
+    return pic_config(L=d.L, ng=d.ng, U=d.U, f=d.f, p=d.p, t_gas=d.t_gas, steps_per_cycle=d.steps_per_cycle,
+                      ksub=d.ksub, c_meta=d.c_meta, seed=int(d.seed if seed is None else seed) & (2 ** 64 - 1),
+                      weight=d.weight, diag_every=d.diag_every if diag_every is None else diag_every,
+                      pair_rounds=d.pair_rounds, sort_every=d.sort_every if sort_every is None else sort_every,
+                      flags=flags, e_ext0=e_ext[0], e_ext1=e_ext[1], table_emin=table[0], table_emax=table[1],
+                      table_n=table[2], max_products=max_products, event_capacity=event_capacity, block=block,
+                      grid=grid, sort_kind=getattr(d, "sort_kind", SORT_CELL) if sort_kind is None else sort_kind)
+
+
+def make_species(species):
+    return (pic_species * 3)(*[pic_species(s.charge, s.mass, s.t0_ev, s.count, s.capacity) for s in species])
+
+
+def make_processes(procs):
+    tabs = [np.ascontiguousarray(p.sigma, dtype=np.float64) for p in procs]
+    arr = (pic_process * max(1, len(procs)))(*[
+        pic_process(p.species, KIND[p.kind], TARGET[p.target], p.e_th, p.target_mass,
+                    t.ctypes.data_as(C.POINTER(C.c_double))) for p, t in zip(procs, tabs)])
+    return arr, tabs
+
+
+# ---------------------------------------------------------------- C ABI, same names
+def pic_version():
+    return lib().pic_version()
+
+
+def pic_query(cfg, sp, pr, nproc):
+    n = C.c_uint64(0)
+    _check(lib().pic_query(C.byref(cfg), sp, pr, nproc, C.byref(n)))
+    return n.value
+
+
+def pic_create(cfg, sp, pr, nproc, workspace_ptr, nbytes, stream_ptr):
+    h = C.c_void_p()
+    _check(lib().pic_create(C.byref(cfg), sp, pr, nproc, C.c_void_p(workspace_ptr), nbytes,
+                            C.c_void_p(stream_ptr), C.byref(h)))
+    return h
+
+
+def pic_destroy(h):
+    _check(lib().pic_destroy(h))
+
+
+def pic_load_uniform(h):
+    _check(lib().pic_load_uniform(h), h)
+
+
+def pic_set_particles(h, s, st, next_id):
+    n = len(st["id"])
+    a = {k: np.ascontiguousarray(st[k], dtype=t) for k, t in
+         (("cell", np.int32), ("off", np.float32), ("vx", np.float32), ("vy", np.float32), ("vz", np.float32),
+          ("id", np.uint32), ("cd", np.int32))}
+    _check(lib().pic_set_particles(h, s, n, _ptr(a["cell"]), _ptr(a["off"]), _ptr(a["vx"]), _ptr(a["vy"]),
+                                   _ptr(a["vz"]), _ptr(a["id"]), _ptr(a["cd"]), int(next_id)), h)
+
+
+def pic_count(h, s):
+    n = C.c_int64(0)
+    _check(lib().pic_count(h, s, C.byref(n)), h)
+    return n.value
+
+
+def pic_get_particles(h, s, cap=None):
+    if cap is None:
+        cap = pic_count(h, s)
+    n = C.c_int64(cap)
+    out = {"cell": np.zeros(cap, np.int32), "off": np.zeros(cap, np.float32), "vx": np.zeros(cap, np.float32),
+           "vy": np.zeros(cap, np.float32), "vz": np.zeros(cap, np.float32), "id": np.zeros(cap, np.uint32),
+           "cd": np.zeros(cap, np.int32)}
+    nid = C.c_uint32(0)
+    _check(lib().pic_get_particles(h, s, C.byref(n), _ptr(out["cell"]), _ptr(out["off"]), _ptr(out["vx"]),
+                                   _ptr(out["vy"]), _ptr(out["vz"]), _ptr(out["id"]), _ptr(out["cd"]),
+                                   C.byref(nid)), h)
+    return {k: v[:n.value] for k, v in out.items()}, nid.value
+
+
+def pic_prepare(h, shift):
+    _check(lib().pic_prepare(h, 1 if shift else 0), h)
+
+
+def pic_set_step(h, step):
+    _check(lib().pic_set_step(h, int(step)), h)
+
+
+def pic_get_step(h):
+    n = C.c_int64(0)
+    _check(lib().pic_get_step(h, C.byref(n)), h)
+    return n.value
+
+
+def pic_step(h, n_steps):
+    _check(lib().pic_step(h, int(n_steps)), h)
+
+
+def pic_sync(h):
+    _check(lib().pic_sync(h), h)
+
+
+def pic_moments(h, ng, reset=False):
+    m = {"sum_q": np.zeros((3, ng + 1)), "sum_phi": np.zeros(ng + 1), "esum": np.zeros((3, ng), np.int64),
+         "ecnt": np.zeros((3, ng), np.int64), "edf": np.zeros((3, NBIN), np.int64),
+         "iedf": np.zeros((3, 2, NBIN), np.int64)}
+    o = pic_moments_out(*[_ptr(m[k]) for k in ("sum_q", "sum_phi", "esum", "ecnt", "edf", "iedf")], 0, 0)
+    _check(lib().pic_moments(h, C.byref(o), 1 if reset else 0), h)
+    m["nacc"], m["ndiag"] = o.nacc, o.ndiag
+    return m
+
+
+def pic_get_hist(h, ng):
+    q = np.zeros((3, ng + 1), np.int64)
+    _check(lib().pic_get_hist(h, _ptr(q)), h)
+    return q
+
+
+def pic_get_field(h, ng):
+    phi = np.zeros(ng + 1)
+    e = np.zeros(ng + 1, np.float32)
+    _check(lib().pic_get_field(h, _ptr(phi), _ptr(e)), h)
+    return phi, e
+
+
+def pic_get_counters(h):
+    c = np.zeros(NCOUNT, np.int64)
+    _check(lib().pic_get_counters(h, _ptr(c)), h)
+    return c
+
+
+def pic_get_events(h, max_records, clear=False):
+    rec = np.zeros((max(1, max_records), 4), np.int64)
+    n = C.c_int64(0)
+    _check(lib().pic_get_events(h, max_records, _ptr(rec), C.byref(n), 1 if clear else 0), h)
+    return rec[:min(n.value, max_records)], n.value
+
+
+def pic_nu_max(h, s):
+    v = C.c_double(0)
+    _check(lib().pic_nu_max(h, s, C.byref(v)), h)
+    return v.value
+
+
+def pic_step_timed(h, n_steps):
+    a, b, c = C.c_double(0), C.c_double(0), C.c_int64(0)
+    _check(lib().pic_step_timed(h, int(n_steps), C.byref(a), C.byref(b), C.byref(c)), h)
+    return a.value, b.value, c.value
+
+
+# ---------------------------------------------------------------- convenience owner of one discharge
+class Discharge:
+    """One discharge on the current GPU: builds the C structs from a workload
+    description (see inputs.Discharge), allocates the workspace as a torch
+    uint8 tensor and runs everything through the C ABI above."""
+
+    def __init__(self, d, procs, species=None, flags=0, e_ext=(0.0, 0.0), seed=None, max_products=None,
+                 event_capacity=0, block=0, grid=0, sort_every=None, diag_every=None, stream=None, sort_kind=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the PIC-MCC path runs only on a gfx950 device")
+        self.d = d
+        self.ng = d.ng
+        self.cfg = make_config(d, flags, e_ext, seed, max_products, event_capacity, block, grid, sort_every,
+                               diag_every, sort_kind=sort_kind)
+        self.species = species if species is not None else d.species()
+        self.sp = make_species(self.species)
+        self.pr, self._tabs = make_processes(procs)
+        self.nproc = len(procs)
+        self.event_capacity = event_capacity
+        nbytes = pic_query(self.cfg, self.sp, self.pr, self.nproc)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.h = pic_create(self.cfg, self.sp, self.pr, self.nproc, self.workspace.data_ptr(), nbytes,
+                            self.stream.cuda_stream)
+
+    def close(self):
+        if getattr(self, "h", None):
+            pic_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_uniform(self):
+        pic_load_uniform(self.h)
+
+    def set_particles(self, s, st, next_id):
+        pic_set_particles(self.h, s, st, next_id)
+
+    def get_particles(self, s):
+        return pic_get_particles(self.h, s)
+
+    def count(self, s):
+        return pic_count(self.h, s)
+
+    def prepare(self, shift=True):
+        pic_prepare(self.h, shift)
+
+    def set_step(self, n):
+        pic_set_step(self.h, n)
+
+    @property
+    def step_index(self):
+        return pic_get_step(self.h)
+
+    def step(self, n=1):
+        pic_step(self.h, n)
+
+    def sync(self):
+        pic_sync(self.h)
+
+    def moments(self, reset=False):
+        return pic_moments(self.h, self.ng, reset)
+
+    def hist(self):
+        return pic_get_hist(self.h, self.ng)
+
+    def field(self):
+        return pic_get_field(self.h, self.ng)
+
+    def counters(self):
+        return pic_get_counters(self.h)
+
+    def clear_events(self):
+        pic_get_events(self.h, 0, True)
+
+    def events(self, clear=True):
+        rec, n = pic_get_events(self.h, self.event_capacity, clear)
+        if n > self.event_capacity:
+            raise RuntimeError(f"event log overflow: {n} > {self.event_capacity}")
+        return rec
+
+    def nu_max(self, s):
+        return pic_nu_max(self.h, s)
+
+    def step_timed(self, n):
+        return pic_step_timed(self.h, n)

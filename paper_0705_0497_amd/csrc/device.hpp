@@ -1,0 +1,122 @@
+// Internal layout shared by the host library (pic.cpp) and the gfx950 kernels
+// (kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <stdint.h>
+
+namespace picmcc {
+
+constexpr int NSP = 3;
+constexpr int MAXPROC = 16;
+constexpr int MAXPROC_SP = 8;      // processes per species
+constexpr int NCOUNT = 40;
+constexpr int NBIN = 256;
+constexpr int CD_MAX = 32767;      // longest stored free flight [steps]
+constexpr int MAXPROD = 1 << 24;   // products per species per step (24-bit local index)
+constexpr int NBKT = 8192;         // parent-key buckets of the product id assignment
+
+// packed cell word of a particle (int32):
+//   bits 0..14 cell, bit 15 capped flight, bits 16..30 countdown, bit 31 dead
+constexpr uint32_t W_CELL = 0x7FFFu;
+constexpr uint32_t W_CAP = 0x8000u;
+constexpr int W_CD_SHIFT = 16;
+constexpr int32_t W_DEAD = -1;
+
+enum { K_ELASTIC = 0, K_EXCITE = 1, K_IONIZE = 2, K_ATTACH = 3, K_CX = 4, K_NEUTRALIZE = 5, K_DETACH = 6 };
+enum { T_O2 = 0, T_O2A = 1, T_GRIDPOS = 2 };
+enum { P_LOAD = 1, P_CAND = 2, P_TARGET = 3, P_PROD = 4, P_PAIR = 5 };
+enum { C_PUSH = 0, C_CAND = 3, C_NULL = 6, C_ABS0 = 9, C_ABSL = 12, C_BORN = 15, C_EVENT = 18,
+       C_PAIRED = 34, C_DEFICIT = 35, C_CLAMP = 36, C_REDRAW = 37 };
+enum { E_CAPACITY = 1, E_IDOVERFLOW = 2, E_NAN = 4 };
+enum { F_EXT_FIELD = 1, F_NO_COLL = 2 };
+
+// device-resident scalars
+struct Scalars {
+  unsigned long long n[NSP];       // occupied slots (live + dead) per species
+  unsigned long long nnew[NSP];    // products appended in the current step
+  unsigned long long cnt[NCOUNT];
+  unsigned long long nev;          // collision events logged
+  uint32_t next_id[NSP];
+  uint32_t err;
+  double numax_neg;                // O- bound of the current ion step [1/s]
+  double pnull_neg;                // 1 - exp(-numax_neg dt_i)
+  float inv_numax_neg;
+  int32_t pair_active;             // pending neutralisation partners
+  uint32_t ticket;                 // last-block-done counter
+  int32_t pad;
+  unsigned long long nsort[NSP];   // slots seen by the running sort
+};
+
+struct Particles {
+  int32_t *w;          // packed cell word
+  float *off, *vx, *vy, *vz;
+  uint32_t *id;
+};
+
+struct ProcDev {
+  int32_t kind, target, tab;       // tab = row of the sigma table
+  float e_th;
+  float scale;                     // n_target / nu_max (constant targets)
+  float inv_mu2;                   // 2 e / mu  (relative speed from energy)
+  float half_mu_e;                 // mu / (2 e) (energy from relative speed)
+  float vt;                        // sqrt(k T / M) of the partner
+  float tm_ratio;                  // 2 m / M (electron elastic loss)
+};
+
+struct Sim {
+  // geometry and drive
+  int32_t ng;
+  double dx, dt, L;
+  double U, f;
+  double eps0, qcharge;            // epsilon_0, e*w*2^-32 (charge per fixed-point unit per m^2)
+  double e_ext0, e_ext1;
+  int32_t flags, ksub;
+  uint64_t seed;
+  // species
+  Particles p[NSP];
+  uint64_t *pkey[NSP];             // (parent species, parent id, local index) of this step's products
+  int32_t *pbkt[NSP];              // bucket of each product's parent key
+  uint64_t *ptmp[NSP];             // keys grouped by bucket during the id assignment
+  int32_t *bcnt;                   // [3][NBKT] products per bucket this step
+  int64_t cap[NSP];
+  int32_t max_products;
+  int32_t charge[NSP];
+  float qmdt[NSP], dtdx[NSP];      // q/m dt_s, dt_s/dx
+  float half_m_e[NSP];             // m / (2 e): energy [eV] from v^2
+  float two_e_m[NSP];              // 2 e / m
+  double mass[NSP];
+  float vt_gas[NSP];               // sqrt(k T_gas / m_s): Maxwellian of newborn ions
+  // processes
+  int32_t nproc_sp[NSP];
+  ProcDev proc[NSP][MAXPROC_SP];
+  const float *sigma;              // [nproc][ntab] FP32
+  const double *hbound;            // [nproc][ntab-1] max(sigma_k, sigma_k+1) g(E_k+1), FP64
+  int32_t ntab;
+  float lnemin, invdlt, emin, emax;
+  double n_o2, c_meta;
+  double nd_e;                     // nu_max(e) dt
+  float nd_ef;                     // the same in FP32
+  const float *ttot_e;             // [ntab] sum over electron processes of scale_p sigma_p
+  unsigned long long *part;        // [grid][ng+1] per-block charge partials
+  long long *blkcnt;               // [grid] live counts / output offsets of the compaction
+  double pnull_pos;                // 1 - exp(-nu_max(O2+) dt_i)
+  double dti;
+  double wd;                       // w 2^-32 / dx : node density per fixed-point unit (interior)
+  float nplus_c;                   // the same in FP32
+  // grid and accumulators
+  unsigned long long *Q;           // [3][ng+1]
+  float *E;                        // [ng+1]
+  double *phi;                     // [ng+1]
+  double *sumQ, *sumphi;           // [3][ng+1], [ng+1]
+  unsigned long long *esum, *ecnt; // [3][ng]
+  unsigned long long *edf, *iedf;  // [3][NBIN], [3][2][NBIN]
+  unsigned long long *nacc;        // [2] nacc, ndiag
+  int32_t *kleft;                  // [ng] neutralisations waiting for a partner
+  unsigned long long *cmin;        // [2][ng] pairing minima
+  int32_t *sortcnt, *sortbase;     // [ng], [ng]
+  Scalars *sc;
+  long long *events;
+  int64_t event_cap;
+  int32_t pair_rounds;
+};
+
+}  // namespace picmcc

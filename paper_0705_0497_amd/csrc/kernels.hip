@@ -1,0 +1,1255 @@
+// gfx950 kernels of the 1D3V oxygen PIC-MCC step.
+//
+// Paper: Bronold et al., "Particle-based modeling of oxygen discharges"
+// (ICPIG 2007), sections 1-2, Table 1, Eq. (1).  One step n:
+//   k_field   charge -> potential -> node field (FP64), cycle sums, product ids
+//   k_push<e> leapfrog push, absorbing walls, null-collision MCC with free
+//             flights counted in steps, products, 64-bit fixed-point CIC deposit
+//   on ion steps: k_push<O2+>, k_ionprep (O- bound), k_push<O->, k_pair rounds
+//   every S steps: counting sort by cell; every D steps: energy moments.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "device.hpp"
+
+namespace picmcc {
+
+// ---------------------------------------------------------------- random numbers
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two 32x32
+// multiplications with the Weyl key schedule.
+struct U4 { uint32_t x, y, z, w; };
+
+__device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                     uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
+    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+  }
+  return {c0, c1, c2, c3};
+}
+
+// stream of one particle: counter (id, step, species|purpose|block, 0), key = seed
+__device__ __forceinline__ U4 draw(const Sim &S, int s, uint32_t id, int64_t step, int purpose, int blk) {
+  return philox(id, (uint32_t)step, ((uint32_t)s << 24) | ((uint32_t)purpose << 16) | (uint32_t)blk, 0u,
+                (uint32_t)S.seed, (uint32_t)(S.seed >> 32));
+}
+
+// (k + 1/2) 2^-23 from the top 23 bits: exact in FP32 and FP64
+__device__ __forceinline__ float unif(uint32_t x) { return fmaf((float)(x >> 9), 0x1p-23f, 0x1p-24f); }
+__device__ __forceinline__ double unifd(uint32_t x) { return ((double)(x >> 9) + 0.5) * 0x1p-23; }
+
+__device__ __forceinline__ void normals(uint32_t a, uint32_t b, float &z0, float &z1) {
+  const float r = sqrtf(-2.0f * logf(unif(a)));
+  float sn, cs;
+  sincospif(2.0f * unif(b), &sn, &cs);
+  z0 = r * cs;
+  z1 = r * sn;
+}
+
+__device__ __forceinline__ void iso_dir(uint32_t a, uint32_t b, float &d0, float &d1, float &d2) {
+  const float ct = 1.0f - 2.0f * unif(a);
+  const float st = sqrtf(fmaxf(0.0f, 1.0f - ct * ct));
+  float sn, cs;
+  sincospif(2.0f * unif(b), &sn, &cs);
+  d0 = ct;
+  d1 = st * cs;
+  d2 = st * sn;
+}
+
+// free flight in steps, 1 + floor(-ln u / (nu_max dt)), stored in the cell word;
+// flights beyond CD_MAX steps are stored capped and redrawn when they expire
+__device__ __forceinline__ uint32_t new_flight(double nd, uint32_t x) {
+  const double tau = nd > 0.0 ? -log(unifd(x)) / nd : (double)CD_MAX;
+  if (tau >= (double)CD_MAX) return ((uint32_t)CD_MAX << W_CD_SHIFT) | W_CAP;
+  return (uint32_t)(1 + (int)floor(tau)) << W_CD_SHIFT;
+}
+
+// ---------------------------------------------------------------- small helpers
+struct TabPos { int i; float w; };
+
+__device__ __forceinline__ TabPos tab_pos(const Sim &S, float ec) {
+  float t = (logf(ec) - S.lnemin) * S.invdlt;
+  t = fminf(fmaxf(t, 0.0f), (float)(S.ntab - 1));
+  const int i = min((int)t, S.ntab - 2);
+  return {i, t - (float)i};
+}
+
+__device__ __forceinline__ float tab_sigma(const float *tab, TabPos tp) {
+  const float a = tab[tp.i], b = tab[tp.i + 1];
+  return fmaf(tp.w, b - a, a);
+}
+
+// CIC weight of node cell+1 in 2^-32 units: rint(off 2^32), exact scaling then RNE
+__device__ __forceinline__ unsigned long long cic_a(float off) {
+  return (unsigned long long)__float2uint_rn(off * 4294967296.0f);
+}
+
+__device__ __forceinline__ void dep_lds(unsigned long long *sQ, int cell, float off) {
+  const unsigned long long a = cic_a(off);
+  atomicAdd(&sQ[cell], 4294967296ull - a);
+  atomicAdd(&sQ[cell + 1], a);
+}
+
+__device__ __forceinline__ void dep_global(unsigned long long *Q, int cell, float off) {
+  const unsigned long long a = cic_a(off);
+  atomicAdd(&Q[cell], 4294967296ull - a);
+  atomicAdd(&Q[cell + 1], a);
+}
+
+__device__ __forceinline__ int ebin(float e) {
+  if (!(e > 0.0f)) return 0;
+  const int b = (int)floorf((log10f(e) + 3.0f) * ((float)NBIN / 6.0f));
+  return min(max(b, 0), NBIN - 1);
+}
+
+__device__ __forceinline__ void log_event(const Sim &S, int64_t step, int s, uint32_t id, int code) {
+  if (S.event_cap <= 0) return;
+  const unsigned long long k = atomicAdd(&S.sc->nev, 1ull);
+  if ((int64_t)k < S.event_cap) {
+    long long *r = S.events + 4 * k;
+    r[0] = step; r[1] = s; r[2] = id; r[3] = code;
+  }
+}
+
+// reserve the slot of a product of species s born from parent (ps, pid).  Its
+// parent key (ps, pid) goes to the id assignment, bucketed by its position in
+// the ordered key space [0, next_id[0]) + [0, next_id[1]) + [0, next_id[2]).
+struct IdSpace { uint64_t off[NSP]; uint64_t total; };
+
+__device__ __forceinline__ IdSpace id_space(const Sim &S) {
+  IdSpace r;
+  uint64_t t = 0;
+  for (int s = 0; s < NSP; ++s) { r.off[s] = t; t += S.sc->next_id[s]; }
+  r.total = t > 0 ? t : 1;
+  return r;
+}
+
+__device__ __forceinline__ int64_t append(const Sim &S, int s, int ps, uint32_t pid, const IdSpace &ids) {
+  // one reservation per wave: the active lanes of this call site take consecutive keys
+  const unsigned long long act = __ballot(1);
+  const int lane = __lane_id();
+  const int leader = __ffsll((long long)act) - 1;
+  unsigned long long base = 0ull;
+  if (lane == leader) base = atomicAdd(&S.sc->nnew[s], (unsigned long long)__popcll(act));
+  base = __shfl(base, leader, 64);
+  const unsigned long long k = base + (unsigned long long)__popcll(act & ((1ull << lane) - 1ull));
+  const int64_t slot = (int64_t)S.sc->n[s] + (int64_t)k;
+  if (k >= (unsigned long long)S.max_products || slot >= S.cap[s]) {
+    atomicOr(&S.sc->err, (uint32_t)E_CAPACITY);
+    return -1;
+  }
+  S.pkey[s][k] = ((uint64_t)ps << 56) | ((uint64_t)pid << 24) | k;
+  const int b = (int)(((ids.off[ps] + pid) * (uint64_t)NBKT) / ids.total);
+  S.pbkt[s][k] = b;
+  atomicAdd(&S.bcnt[s * NBKT + b], 1);
+  return slot;
+}
+
+__device__ __forceinline__ void put(const Particles &P, int64_t i, int32_t w, float off, float vx, float vy,
+                                    float vz) {
+  P.w[i] = w; P.off[i] = off; P.vx[i] = vx; P.vy[i] = vy; P.vz[i] = vz;
+}
+
+// ---------------------------------------------------------------- block scans
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const T t = __shfl_up(v, o, 64);
+    if (lane >= o) v += t;
+  }
+  return v;
+}
+
+// exclusive scan over the block (BS a multiple of 64); buf holds BS/64 entries
+template <int BS, typename T>
+__device__ T block_exclusive_scan(T v, T *buf, T &total) {
+  constexpr int NW = BS / 64;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const T inc = wave_incl_scan(v);
+  if (lane == 63) buf[wid] = inc;
+  __syncthreads();
+  if (wid == 0) {
+    T x = lane < NW ? buf[lane] : T(0);
+    x = wave_incl_scan(x);
+    if (lane < NW) buf[lane] = x;
+  }
+  __syncthreads();
+  const T pre = wid ? buf[wid - 1] : T(0);
+  total = buf[NW - 1];
+  __syncthreads();
+  return pre + inc - v;
+}
+
+// ---------------------------------------------------------------- field solve
+// -eps0 (phi[j-1] - 2 phi[j] + phi[j+1]) / dx^2 = rho[j], phi[0] = U sin(2 pi f t_n),
+// phi[ng] = 0.  Written as D[j+1/2] = D[1/2] + sum_{m=1..j} rho[m] dx (exact int64
+// prefix of the node charges), phi[j] = phi0 - (dx/eps0) sum_{m<j} D[m+1/2]; phi[ng] = 0
+// fixes D[1/2].  Same linear system as the tridiagonal one, solved by two scans.
+template <int BS>
+__device__ void field_block(const Sim &S, int64_t step, int mode) {
+  __shared__ long long sI[BS];
+  __shared__ double sJ[BS];
+  const int ng = S.ng, nn = ng + 1, t = threadIdx.x;
+  const int per = (nn + BS - 1) / BS;
+  const int j0 = min(t * per, nn), j1 = min(j0 + per, nn);
+  const bool ion = (step % S.ksub) == 0;
+  const unsigned long long *Qe = S.Q, *Qp = S.Q + nn, *Qn = S.Q + 2 * nn;
+  if (S.flags & F_EXT_FIELD) {
+    for (int j = j0; j < j1; ++j) {
+      S.E[j] = (float)(S.e_ext0 + S.e_ext1 * ((double)j * S.dx - 0.5 * S.L));
+      S.phi[j] = 0.0;
+    }
+  }
+  // node charge q_j in fixed point; the interior part enters the first scan
+  long long loc = 0;
+  for (int j = j0; j < j1; ++j) {
+    const long long q = (long long)S.charge[0] * (long long)Qe[j] + (long long)S.charge[1] * (long long)Qp[j] +
+                        (long long)S.charge[2] * (long long)Qn[j];
+    if (j > 0 && j < ng) loc += q;
+  }
+  long long itot;
+  const long long ibase = block_exclusive_scan<BS, long long>(loc, sI, itot);
+  // second scan: J_j = sum_{m<j} I_m
+  double jloc = 0.0;
+  {
+    long long run = ibase;
+    for (int j = j0; j < j1; ++j) {
+      const long long q = (long long)S.charge[0] * (long long)Qe[j] + (long long)S.charge[1] * (long long)Qp[j] +
+                          (long long)S.charge[2] * (long long)Qn[j];
+      if (j > 0 && j < ng) run += q;
+      if (j < ng) jloc += (double)run;
+    }
+  }
+  double jtot;
+  const double jbase = block_exclusive_scan<BS, double>(jloc, sJ, jtot);
+  if (!(S.flags & F_EXT_FIELD)) {
+    const double c = S.qcharge;            // e w 2^-32: charge per unit area per fixed-point unit
+    const double phi0 = S.U * sin(2.0 * M_PI * S.f * ((double)step * S.dt));
+    const double d_half = (phi0 * S.eps0 / S.dx - c * jtot) / (double)ng;
+    const double k = S.dx / S.eps0;
+    long long run = ibase;
+    double jrun = jbase;
+    for (int j = j0; j < j1; ++j) {
+      const long long q = (long long)S.charge[0] * (long long)Qe[j] + (long long)S.charge[1] * (long long)Qp[j] +
+                          (long long)S.charge[2] * (long long)Qn[j];
+      const long long iprev = run;                 // I_{j-1}
+      if (j > 0 && j < ng) run += q;               // I_j
+      const double phi = (j == ng) ? 0.0 : phi0 - k * ((double)j * d_half + c * jrun);
+      double e;
+      if (j == 0) e = (d_half - c * (double)q) / S.eps0;
+      else if (j == ng) e = (d_half + c * (double)iprev + c * (double)q) / S.eps0;
+      else e = (2.0 * d_half + c * ((double)iprev + (double)run)) / (2.0 * S.eps0);
+      S.phi[j] = phi;
+      S.E[j] = (float)e;
+      if (j < ng) jrun += (double)run;
+    }
+  }
+  if (mode != 0) return;
+  // cycle sums of the state this solve saw, then clear what this step rebuilds
+  for (int j = j0; j < j1; ++j) {
+    S.sumQ[j] += (double)Qe[j];
+    S.sumQ[nn + j] += (double)Qp[j];
+    S.sumQ[2 * nn + j] += (double)Qn[j];
+    S.sumphi[j] += S.phi[j];
+    S.Q[j] = 0ull;
+    if (ion) { S.Q[nn + j] = 0ull; S.Q[2 * nn + j] = 0ull; }
+  }
+  if (t == 0) S.nacc[0] += 1ull;
+}
+
+// ids of the previous step's products: per species, next_id + rank of the
+// parent key (parent species, parent id).  The keys were counted per bucket of
+// the ordered key space when they were appended; here the buckets are scanned,
+// the keys grouped by bucket and each ranked inside its (small) bucket.
+template <int BS>
+__device__ void fixup_block(const Sim &S, int s, int *lds) {
+  const unsigned long long nnew = S.sc->nnew[s];
+  if (nnew == 0) return;
+  const int64_t n = (int64_t)S.sc->n[s];
+  int64_t nval = (int64_t)nnew;
+  if (nval > S.max_products) nval = S.max_products;
+  if (nval > S.cap[s] - n) nval = S.cap[s] - n;
+  int *bstart = lds, *fill = lds + NBKT;
+  __shared__ long long scan_buf[BS];
+  constexpr int PER = NBKT / BS;
+  int *cnt = S.bcnt + s * NBKT;
+  long long loc = 0;
+  for (int j = 0; j < PER; ++j) loc += cnt[threadIdx.x * PER + j];
+  long long tot;
+  long long run = block_exclusive_scan<BS, long long>(loc, scan_buf, tot);
+  for (int j = 0; j < PER; ++j) {
+    const int b = threadIdx.x * PER + j;
+    bstart[b] = (int)run;
+    run += cnt[b];
+    cnt[b] = 0;
+    fill[b] = 0;
+  }
+  __syncthreads();
+  if (tot != nval) {                 // counts and keys disagree: refuse rather than scatter out of range
+    if (threadIdx.x == 0) {
+      atomicOr(&S.sc->err, (uint32_t)E_CAPACITY);
+      S.sc->nnew[s] = 0ull;
+    }
+    return;
+  }
+  uint64_t *tmp = S.ptmp[s];
+  for (int64_t k = threadIdx.x; k < nval; k += BS) {
+    const int b = S.pbkt[s][k];
+    tmp[bstart[b] + atomicAdd(&fill[b], 1)] = S.pkey[s][k];
+  }
+  __threadfence_block();
+  __syncthreads();
+  const uint32_t next = S.sc->next_id[s];
+  for (int64_t q = threadIdx.x; q < nval; q += BS) {
+    int lo = 0, hi = NBKT - 1;                     // bucket holding position q
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (bstart[mid] <= q) lo = mid; else hi = mid - 1;
+    }
+    const int64_t b0 = bstart[lo], b1 = lo + 1 < NBKT ? bstart[lo + 1] : nval;
+    const uint64_t key = tmp[q], parent = key >> 24;
+    int64_t rank = b0;
+    for (int64_t r = b0; r < b1; ++r) rank += (tmp[r] >> 24) < parent;
+    S.p[s].id[n + (int64_t)(key & 0xFFFFFFull)] = next + (uint32_t)rank;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if ((uint64_t)next + (uint64_t)nval > 0xFFFFFFFFull) atomicOr(&S.sc->err, (uint32_t)E_IDOVERFLOW);
+    S.sc->next_id[s] = next + (uint32_t)nval;
+    S.sc->n[s] = (unsigned long long)(n + nval);
+    S.sc->nnew[s] = 0ull;
+  }
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_field(Sim S, int64_t step, int mode) {
+  extern __shared__ int dyn_fix[];
+  if (blockIdx.x == 0) field_block<BS>(S, step, mode);
+  else fixup_block<BS>(S, blockIdx.x - 1, dyn_fix);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_fixup(Sim S) {
+  extern __shared__ int dyn_fix[];
+  fixup_block<BS>(S, blockIdx.x, dyn_fix);
+}
+
+// ---------------------------------------------------------------- particle step
+// A block owns a contiguous chunk of the store (a multiple of GROUP slots).  Per
+// pass each thread takes GROUP consecutive particles with 128-bit loads and
+// stores, keeps consecutive deposits into one cell in registers, and queues the
+// slots of collision candidates in LDS; after the pass the whole block works the
+// queue with all lanes.  The block's charge histogram stays in LDS and is written
+// out as one partial per block; k_reduce adds the partials into the species
+// histogram, so no global atomics are needed for the bulk of the charge.
+constexpr int GROUP = 8;
+constexpr int MAXGRID = 2048;
+
+// energies of particles absorbed at x = 0 / x = L, per block
+struct WallHist { unsigned int iedf[2][NBIN]; };
+
+struct PushShared {
+  unsigned long long *Q;   // [nn] charge of this species, block-local
+  float *E;                // [nn] node field
+  float *N;                // [nn] O2+ node density (O- kernel)
+  float *tab;              // [np][ntab]
+  float *ttot;             // [ntab] sum_p scale_p sigma_p (electrons: early null test)
+  unsigned short *queue;   // [GROUP BS] candidate slots relative to the pass base
+};
+
+__device__ __forceinline__ size_t align_up(size_t x) { return (x + 15) & ~(size_t)15; }
+
+struct BlockCounts { unsigned int c[NCOUNT]; };
+
+// adds the number of active lanes to one block counter with a single LDS atomic
+__device__ __forceinline__ void count_lanes(BlockCounts &bc, int idx) {
+  const unsigned long long act = __ballot(1);
+  if (__lane_id() == __ffsll((long long)act) - 1) atomicAdd(&bc.c[idx], (unsigned int)__popcll(act));
+}
+
+// consecutive deposits into one cell, kept in registers
+struct DepRun {
+  int cell;
+  unsigned long long l, r;
+  __device__ __forceinline__ DepRun() : cell(-1), l(0ull), r(0ull) {}
+  __device__ __forceinline__ void flush(unsigned long long *sQ) {
+    if (cell >= 0) { atomicAdd(&sQ[cell], l); atomicAdd(&sQ[cell + 1], r); }
+    cell = -1; l = 0ull; r = 0ull;
+  }
+  __device__ __forceinline__ void add(unsigned long long *sQ, int c, float off) {
+    const unsigned long long a = cic_a(off);
+    if (c != cell) { flush(sQ); cell = c; }
+    l += 4294967296ull - a;
+    r += a;
+  }
+};
+
+// one product of species s from parent (ps, pid)
+__device__ __forceinline__ void emit(const Sim &S, int s, int ps, uint32_t pid, int32_t w, float off, float vx,
+                                     float vy, float vz) {
+  const int64_t slot = append(S, s, ps, pid, id_space(S));
+  if (slot >= 0) put(S.p[s], slot, w, off, vx, vy, vz);
+}
+
+// free flight in steps from an FP32 draw (the 1e-6 decision band covers FP32)
+__device__ __forceinline__ uint32_t new_flight_f(float ndf, uint32_t x) {
+  const float tau = ndf > 0.0f ? -logf(unif(x)) / ndf : (float)CD_MAX;
+  if (!(tau < (float)CD_MAX)) return ((uint32_t)CD_MAX << W_CD_SHIFT) | W_CAP;
+  return (uint32_t)(1 + (int)tau) << W_CD_SHIFT;
+}
+
+// electron collision at the end of a free flight; the post-push state is in memory
+__device__ void collide_electron(const Sim &S, int64_t step, int64_t i, PushShared sh, BlockCounts &bc) {
+  const Particles &P = S.p[0];
+  const int32_t w = P.w[i];
+  const float off = P.off[i];
+  const uint32_t id = P.id[i];
+  float vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
+  const int cell = w & (int32_t)W_CELL;
+  const U4 c = draw(S, 0, id, step, P_CAND, 0);
+  const uint32_t flight = new_flight_f(S.nd_ef, c.x);
+  if (w & (int32_t)W_CAP) {                    // capped flight: redraw, no collision
+    P.w[i] = cell | (int32_t)flight;
+    dep_lds(sh.Q, cell, off);
+    count_lanes(bc, C_REDRAW);
+    log_event(S, step, 0, id, -2);
+    return;
+  }
+  count_lanes(bc, C_CAND + 0);
+  const float v2 = vx * vx + vy * vy + vz * vz;
+  const float e = S.half_m_e[0] * v2;
+  float ec = e;
+  bool cl = false;
+  if (ec < S.emin) { ec = S.emin; cl = true; }
+  else if (ec > S.emax) { ec = S.emax; cl = true; }
+  if (cl) count_lanes(bc, C_CLAMP);
+  const float g = cl ? sqrtf(S.two_e_m[0] * ec) : sqrtf(v2);
+  const TabPos tp = tab_pos(S, ec);
+  const float target = unif(c.y);
+  int chosen = -1, kind = 0;
+  float eth = 0.0f, tmr = 0.0f;
+  // upper bound of the total collision frequency: most candidates are null
+  const float bound = fmaf(tp.w, sh.ttot[tp.i + 1] - sh.ttot[tp.i], sh.ttot[tp.i]) * g;
+  if (target < bound * 1.000001f) {
+    float acc = 0.0f;
+    const int np = S.nproc_sp[0];
+    for (int k = 0; k < np; ++k) {
+      const ProcDev &pd = S.proc[0][k];
+      const float sg = ec < pd.e_th ? 0.0f : tab_sigma(sh.tab + k * S.ntab, tp);
+      acc = fmaf(pd.scale * sg, g, acc);
+      if (target < acc) { chosen = pd.tab; kind = pd.kind; eth = pd.e_th; tmr = pd.tm_ratio; break; }
+    }
+  }
+  log_event(S, step, 0, id, chosen);
+  if (chosen < 0) {
+    P.w[i] = cell | (int32_t)flight;
+    dep_lds(sh.Q, cell, off);
+    count_lanes(bc, C_NULL + 0);
+    return;
+  }
+  atomicAdd(&bc.c[C_EVENT + chosen], 1u);
+  float d0, d1, d2;
+  iso_dir(c.z, c.w, d0, d1, d2);
+  float enew;
+  if (kind == K_ELASTIC) {
+    const float vm = sqrtf(v2);
+    const float cchi = vm > 0.0f ? (vx * d0 + vy * d1 + vz * d2) / vm : 0.0f;
+    enew = e * (1.0f - tmr * (1.0f - cchi));
+  } else if (kind == K_EXCITE) {
+    enew = e - eth;
+  } else if (kind == K_IONIZE) {
+    const U4 p0 = draw(S, 0, id, step, P_PROD, 0);
+    const U4 p1 = draw(S, 0, id, step, P_PROD, 1);
+    const float er = e - eth, r = unif(p0.x);
+    enew = (1.0f - r) * er;
+    {                                          // secondary electron, isotropic, energy r E_r
+      float s0, s1, s2;
+      iso_dir(p0.y, p0.z, s0, s1, s2);
+      const float vm = sqrtf(S.two_e_m[0] * fmaxf(r * er, 0.0f));
+      emit(S, 0, 0, id, cell | (int32_t)new_flight_f(S.nd_ef, p0.w), off, vm * s0, vm * s1, vm * s2);
+      dep_lds(sh.Q, cell, off);
+      count_lanes(bc, C_BORN + 0);
+    }
+    {                                          // O2+ from the 300 K reservoir
+      float z0, z1, z2, z3;
+      normals(p1.x, p1.y, z0, z1);
+      normals(p1.z, p1.w, z2, z3);
+      const float vt = S.vt_gas[1];
+      emit(S, 1, 0, id, cell, off, vt * z0, vt * z1, vt * z2);
+      dep_global(S.Q + (size_t)(S.ng + 1), cell, off);
+      count_lanes(bc, C_BORN + 1);
+    }
+  } else {                                     // attachment: the electron becomes an O-
+    const U4 p1 = draw(S, 0, id, step, P_PROD, 1);
+    float z0, z1, z2, z3;
+    normals(p1.x, p1.y, z0, z1);
+    normals(p1.z, p1.w, z2, z3);
+    const float vt = S.vt_gas[2];
+    emit(S, 2, 0, id, cell, off, vt * z0, vt * z1, vt * z2);
+    dep_global(S.Q + (size_t)2 * (S.ng + 1), cell, off);
+    count_lanes(bc, C_BORN + 2);
+    P.w[i] = W_DEAD;
+    return;
+  }
+  const float vn = sqrtf(S.two_e_m[0] * fmaxf(enew, 0.0f));
+  P.w[i] = cell | (int32_t)flight;
+  P.vx[i] = vn * d0;
+  P.vy[i] = vn * d1;
+  P.vz[i] = vn * d2;
+  dep_lds(sh.Q, cell, off);
+}
+
+// ion collision candidate: O2+ charge exchange; O- neutralisation against the
+// O2+ grid density or associative detachment on O2(a), Eq. (1)
+template <int S_>
+__device__ void collide_ion(const Sim &S, int64_t step, int64_t i, PushShared sh, BlockCounts &bc,
+                            float inv_numax) {
+  const Particles &P = S.p[S_];
+  const int32_t w = P.w[i];
+  const float off = P.off[i];
+  const uint32_t id = P.id[i];
+  const float vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
+  const int cell = w & (int32_t)W_CELL;
+  count_lanes(bc, C_CAND + S_);
+  const U4 c = draw(S, S_, id, step, P_CAND, 0);
+  const U4 t = draw(S, S_, id, step, P_TARGET, 0);
+  float z0, z1, z2, z3;
+  normals(t.x, t.y, z0, z1);
+  normals(t.z, t.w, z2, z3);
+  const float target = unif(c.y);
+  float acc = 0.0f, erel_c = 0.0f, pvx = 0.0f, pvy = 0.0f, pvz = 0.0f;
+  int chosen = -1, kind = 0;
+  const int np = S.nproc_sp[S_];
+  for (int k = 0; k < np; ++k) {
+    const ProcDev &pd = S.proc[S_][k];
+    const float ux = pd.vt * z0, uy = pd.vt * z1, uz = pd.vt * z2;
+    const float gx = vx - ux, gy = vy - uy, gz = vz - uz;
+    const float g2 = gx * gx + gy * gy + gz * gz;
+    const float erel = pd.half_mu_e * g2;                // relative kinetic energy [eV]
+    float ec = erel;
+    bool cl = false;
+    if (ec < S.emin) { ec = S.emin; cl = true; }
+    else if (ec > S.emax) { ec = S.emax; cl = true; }
+    if (cl) count_lanes(bc, C_CLAMP);
+    const float g = cl ? sqrtf(pd.inv_mu2 * ec) : sqrtf(g2);
+    float dens;
+    if (pd.target == T_GRIDPOS) dens = fmaf(off, sh.N[cell + 1] - sh.N[cell], sh.N[cell]) * inv_numax;
+    else dens = pd.scale * (S_ == 2 ? inv_numax : 1.0f);
+    const float sg = ec < pd.e_th ? 0.0f : tab_sigma(sh.tab + k * S.ntab, tab_pos(S, ec));
+    acc = fmaf(dens * sg, g, acc);
+    if (chosen < 0 && target < acc) {
+      chosen = pd.tab; kind = pd.kind; erel_c = erel; pvx = ux; pvy = uy; pvz = uz;
+    }
+  }
+  log_event(S, step, S_, id, chosen);
+  if (chosen < 0) {
+    P.w[i] = cell;
+    dep_lds(sh.Q, cell, off);
+    count_lanes(bc, C_NULL + S_);
+    return;
+  }
+  atomicAdd(&bc.c[C_EVENT + chosen], 1u);
+  if (kind == K_CX) {                          // the ion leaves with the neutral's velocity
+    P.w[i] = cell;
+    P.vx[i] = pvx; P.vy[i] = pvy; P.vz[i] = pvz;
+    dep_lds(sh.Q, cell, off);
+  } else if (kind == K_NEUTRALIZE) {           // partner O2+ removed by the pairing rounds
+    P.w[i] = W_DEAD;
+    atomicAdd(&S.kleft[cell], 1);
+    S.sc->pair_active = 1;
+  } else {                                     // K_DETACH: electron with the relative energy
+    const U4 p0 = draw(S, S_, id, step, P_PROD, 0);
+    float d0, d1, d2;
+    iso_dir(p0.y, p0.z, d0, d1, d2);
+    const float vm = sqrtf(S.two_e_m[0] * erel_c);
+    emit(S, 0, S_, id, cell | (int32_t)new_flight_f(S.nd_ef, p0.w), off, vm * d0, vm * d1, vm * d2);
+    dep_global(S.Q, cell, off);
+    count_lanes(bc, C_BORN + 0);
+    P.w[i] = W_DEAD;
+  }
+}
+
+__device__ __forceinline__ int64_t push_chunk(int64_t N, int grid) {
+  int64_t chunk = (N + grid - 1) / grid;
+  return (chunk + GROUP - 1) / GROUP * GROUP;
+}
+
+template <int BS, int S_>
+__global__ __launch_bounds__(BS) void k_push(Sim S, int64_t step) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ int qn[2];
+  __shared__ BlockCounts bc;
+  __shared__ WallHist wall;
+  const int ng = S.ng, nn = ng + 1;
+  const int64_t N = (int64_t)S.sc->n[S_];
+  const int64_t chunk = push_chunk(N, gridDim.x);
+  const int64_t begin = (int64_t)blockIdx.x * chunk;
+  const int64_t end = min(N, begin + chunk);
+  if (begin >= end) return;
+  const int np = S.nproc_sp[S_];
+  PushShared sh;
+  size_t o = 0;
+  sh.Q = (unsigned long long *)(smem + o); o = align_up(o + sizeof(unsigned long long) * nn);
+  sh.E = (float *)(smem + o); o = align_up(o + sizeof(float) * nn);
+  sh.N = (float *)(smem + o); if (S_ == 2) o = align_up(o + sizeof(float) * nn);
+  sh.tab = (float *)(smem + o); o = align_up(o + sizeof(float) * np * S.ntab);
+  sh.ttot = (float *)(smem + o); if (S_ == 0) o = align_up(o + sizeof(float) * S.ntab);
+  sh.queue = (unsigned short *)(smem + o);
+  for (int j = threadIdx.x; j < 2 * NBIN; j += BS) wall.iedf[j / NBIN][j % NBIN] = 0u;
+  for (int j = threadIdx.x; j < nn; j += BS) {
+    sh.Q[j] = 0ull;
+    sh.E[j] = S.E[j];
+    if (S_ == 2) sh.N[j] = S.nplus_c * ((j == 0 || j == ng) ? 2.0f : 1.0f) * (float)S.Q[nn + j];
+  }
+  for (int k = 0; k < np; ++k)
+    for (int j = threadIdx.x; j < S.ntab; j += BS) sh.tab[k * S.ntab + j] = S.sigma[S.proc[S_][k].tab * S.ntab + j];
+  if (S_ == 0)
+    for (int j = threadIdx.x; j < S.ntab; j += BS) sh.ttot[j] = S.ttot_e[j];
+  for (int k = threadIdx.x; k < NCOUNT; k += BS) bc.c[k] = 0u;
+  if (threadIdx.x == 0) { qn[0] = 0; qn[1] = 0; }
+  float inv_numax = 0.0f;
+  double pnull = 0.0;
+  if (S_ == 1) pnull = S.pnull_pos;
+  if (S_ == 2) { inv_numax = S.sc->inv_numax_neg; pnull = S.sc->pnull_neg; }
+  __syncthreads();
+
+  const Particles &P = S.p[S_];
+  const float qmdt = S.qmdt[S_], dtdx = S.dtdx[S_];
+  const bool nocoll = (S.flags & F_NO_COLL) != 0;
+  const int lane = threadIdx.x & 63;
+  unsigned int npush = 0;
+  DepRun run;
+  int par = 0;
+  for (int64_t base = begin; base < end; base += (int64_t)GROUP * BS, par ^= 1) {
+    const int64_t i0 = base + (int64_t)GROUP * threadIdx.x;
+    unsigned int cmask = 0u;
+    if (i0 < end) {
+      const int nv = (int)min((int64_t)GROUP, end - i0);
+      int32_t w[GROUP];
+      float off[GROUP], vx[GROUP];
+      uint32_t id[GROUP];
+      {
+        const int4 wa = *reinterpret_cast<const int4 *>(P.w + i0), wb = *reinterpret_cast<const int4 *>(P.w + i0 + 4);
+        const float4 oa = *reinterpret_cast<const float4 *>(P.off + i0), ob = *reinterpret_cast<const float4 *>(P.off + i0 + 4);
+        const float4 va = *reinterpret_cast<const float4 *>(P.vx + i0), vb = *reinterpret_cast<const float4 *>(P.vx + i0 + 4);
+        w[0] = wa.x; w[1] = wa.y; w[2] = wa.z; w[3] = wa.w; w[4] = wb.x; w[5] = wb.y; w[6] = wb.z; w[7] = wb.w;
+        off[0] = oa.x; off[1] = oa.y; off[2] = oa.z; off[3] = oa.w; off[4] = ob.x; off[5] = ob.y; off[6] = ob.z; off[7] = ob.w;
+        vx[0] = va.x; vx[1] = va.y; vx[2] = va.z; vx[3] = va.w; vx[4] = vb.x; vx[5] = vb.y; vx[6] = vb.z; vx[7] = vb.w;
+        if (S_ != 0 && !nocoll && pnull > 0.0) {
+          const uint4 ia = *reinterpret_cast<const uint4 *>(P.id + i0), ib = *reinterpret_cast<const uint4 *>(P.id + i0 + 4);
+          id[0] = ia.x; id[1] = ia.y; id[2] = ia.z; id[3] = ia.w; id[4] = ib.x; id[5] = ib.y; id[6] = ib.z; id[7] = ib.w;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < GROUP; ++k) {
+        if (k >= nv || w[k] < 0) continue;
+        ++npush;
+        const int cell = w[k] & (int32_t)W_CELL;
+        // gather (linear weighting), leapfrog velocity then position
+        const float e0 = sh.E[cell], e1 = sh.E[cell + 1];
+        const float v = fmaf(qmdt, fmaf(off[k], e1 - e0, e0), vx[k]);
+        const float xn = fmaf(v, dtdx, off[k]);
+        vx[k] = v;
+        if (!(fabsf(xn) < 1.0e9f)) {
+          atomicOr(&S.sc->err, (uint32_t)E_NAN);
+          w[k] = W_DEAD;
+          continue;
+        }
+        const float fl = floorf(xn);
+        int nc = cell + (int)fl;
+        float no = xn - fl;
+        if (no >= 1.0f) { nc += 1; no -= 1.0f; }
+        off[k] = no;
+        if (nc < 0 || nc >= ng) {                      // absorbed by an electrode
+          const int side = nc < 0 ? 0 : 1;
+          const float vy = P.vy[i0 + k], vz = P.vz[i0 + k];
+          const float en = S.half_m_e[S_] * (v * v + vy * vy + vz * vz);
+          atomicAdd(&wall.iedf[side][ebin(en)], 1u);
+          atomicAdd(&bc.c[(side ? C_ABSL : C_ABS0) + S_], 1u);
+          w[k] = W_DEAD;
+          if (S.event_cap > 0) log_event(S, step, S_, P.id[i0 + k], -3);
+          continue;
+        }
+        if (S_ == 0) {
+          const int cd = w[k] >> W_CD_SHIFT;
+          const int cdn = nocoll ? cd : cd - 1;
+          w[k] = nc | (w[k] & (int32_t)W_CAP) | (cdn << W_CD_SHIFT);
+          if (cdn > 0 || nocoll) run.add(sh.Q, nc, no);
+          else cmask |= 1u << k;
+        } else {
+          w[k] = nc;
+          bool cand = false;
+          if (!nocoll && pnull > 0.0) cand = (double)unif(draw(S, S_, id[k], step, P_CAND, 0).x) < pnull;
+          if (cand) cmask |= 1u << k;
+          else run.add(sh.Q, nc, no);
+        }
+      }
+      if (nv == GROUP) {
+        *reinterpret_cast<int4 *>(P.w + i0) = make_int4(w[0], w[1], w[2], w[3]);
+        *reinterpret_cast<int4 *>(P.w + i0 + 4) = make_int4(w[4], w[5], w[6], w[7]);
+        *reinterpret_cast<float4 *>(P.off + i0) = make_float4(off[0], off[1], off[2], off[3]);
+        *reinterpret_cast<float4 *>(P.off + i0 + 4) = make_float4(off[4], off[5], off[6], off[7]);
+        *reinterpret_cast<float4 *>(P.vx + i0) = make_float4(vx[0], vx[1], vx[2], vx[3]);
+        *reinterpret_cast<float4 *>(P.vx + i0 + 4) = make_float4(vx[4], vx[5], vx[6], vx[7]);
+      } else {
+        for (int k = 0; k < nv; ++k) { P.w[i0 + k] = w[k]; P.off[i0 + k] = off[k]; P.vx[i0 + k] = vx[k]; }
+      }
+    }
+    // queue the candidates: one LDS atomic per wave
+    const int mine = __popc(cmask);
+    int incl = wave_incl_scan(mine);
+    int wbase = 0;
+    if (lane == 63 && incl > 0) wbase = atomicAdd(&qn[par], incl);
+    wbase = __shfl(wbase, 63, 64);
+    int q = wbase + incl - mine;
+    for (unsigned int m = cmask; m; m &= m - 1) sh.queue[q++] = (unsigned short)(i0 - base + __ffs(m) - 1);
+    __syncthreads();
+    const int nq = qn[par];
+    if (threadIdx.x == 0) qn[par ^ 1] = 0;     // counter of the next pass, unused since the last barrier
+    for (int k = threadIdx.x; k < nq; k += BS) {
+      if (S_ == 0) collide_electron(S, step, base + sh.queue[k], sh, bc);
+      else collide_ion<S_>(S, step, base + sh.queue[k], sh, bc, inv_numax);
+    }
+    __syncthreads();
+  }
+  run.flush(sh.Q);
+  atomicAdd(&bc.c[C_PUSH + S_], npush);
+  __syncthreads();
+  unsigned long long *part = S.part + (size_t)blockIdx.x * nn;
+  for (int j = threadIdx.x; j < nn; j += BS) part[j] = sh.Q[j];
+  for (int j = threadIdx.x; j < 2 * NBIN; j += BS)
+    if (wall.iedf[j / NBIN][j % NBIN])
+      atomicAdd(&S.iedf[(size_t)S_ * 2 * NBIN + j], (unsigned long long)wall.iedf[j / NBIN][j % NBIN]);
+  for (int k = threadIdx.x; k < NCOUNT; k += BS)
+    if (bc.c[k]) atomicAdd(&S.sc->cnt[k], (unsigned long long)bc.c[k]);
+}
+
+// Q[s] += sum of the partial histograms of the blocks that had particles
+template <int BS>
+__global__ __launch_bounds__(BS) void k_reduce(Sim S, int s, int push_grid) {
+  const int nn = S.ng + 1;
+  const int j = blockIdx.x * BS + threadIdx.x;
+  if (j >= nn) return;
+  const int64_t N = (int64_t)S.sc->n[s];
+  const int64_t chunk = push_chunk(N, push_grid);
+  const int used = chunk > 0 ? (int)((N + chunk - 1) / chunk) : 0;
+  unsigned long long sum = 0ull;
+  for (int b = blockIdx.y; b < used; b += gridDim.y) sum += S.part[(size_t)b * nn + j];
+  if (sum) atomicAdd(&S.Q[(size_t)s * nn + j], sum);
+}
+
+// O- bound of this ion step: nu_max = max_k sum_p n_p H_p[k], with n = the
+// largest O2+ node density for neutralisation and C n(O2) for detachment
+template <int BS>
+__global__ __launch_bounds__(BS) void k_ionprep(Sim S) {
+  __shared__ double red[BS];
+  const int ng = S.ng, nn = ng + 1;
+  double nmax = 0.0;
+  const double c = (double)S.nplus_c;
+  for (int j = threadIdx.x; j < nn; j += BS) {
+    const double v = (double)S.Q[nn + j] * ((j == 0 || j == ng) ? 2.0 : 1.0);
+    nmax = fmax(nmax, v);
+  }
+  red[threadIdx.x] = nmax;
+  __syncthreads();
+  for (int o = BS / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  nmax = red[0] * S.wd;
+  __syncthreads();
+  double best = 0.0;
+  const int np = S.nproc_sp[2];
+  for (int k = threadIdx.x; k < S.ntab - 1; k += BS) {
+    double sum = 0.0;
+    for (int p = 0; p < np; ++p) {
+      const ProcDev &pd = S.proc[2][p];
+      const double n = pd.target == T_GRIDPOS ? nmax : (pd.target == T_O2A ? S.c_meta * S.n_o2 : S.n_o2);
+      sum += n * S.hbound[(size_t)pd.tab * (S.ntab - 1) + k];
+    }
+    best = fmax(best, sum);
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int o = BS / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double nu = red[0];
+    S.sc->numax_neg = nu;
+    S.sc->pnull_neg = 1.0 - exp(-nu * S.dti);
+    S.sc->inv_numax_neg = nu > 0.0 ? (float)(1.0 / nu) : 0.0f;
+    (void)c;
+  }
+}
+
+// Pairing round r of an ion step.  Every neutralised O- in cell j removes one
+// pre-step O2+ of cell j: round r removes the winner of round r-1 (smallest key
+// (pairing draw, id) among the O2+ left in the cell) and finds the next minimum.
+// The last block to finish settles the per-cell bookkeeping.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_pair(Sim S, int64_t step, int r) {
+  if (!S.sc->pair_active) return;
+  const int ng = S.ng, nn = ng + 1, R = S.pair_rounds;
+  unsigned long long *cur = S.cmin + (size_t)(r & 1) * ng;
+  unsigned long long *prev = S.cmin + (size_t)((r + 1) & 1) * ng;
+  const Particles &P = S.p[1];
+  const int64_t N = (int64_t)S.sc->n[1];
+  unsigned long long *Qp = S.Q + nn;
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
+    const int32_t w = P.w[i];
+    if (w < 0) continue;
+    const int c = w & (int32_t)W_CELL;
+    const bool want_prev = r > 0 && prev[c] != ~0ull;
+    const bool want_cur = r < R && S.kleft[c] > 0;
+    if (!want_prev && !want_cur) continue;
+    const uint32_t id = P.id[i];
+    const unsigned long long key = ((unsigned long long)draw(S, 1, id, step, P_PAIR, 0).x << 32) | id;
+    if (want_prev && key == prev[c]) {
+      const float off = P.off[i];
+      const unsigned long long a = cic_a(off);
+      atomicAdd(&Qp[c], (unsigned long long)(-(long long)(4294967296ull - a)));
+      atomicAdd(&Qp[c + 1], (unsigned long long)(-(long long)a));
+      P.w[i] = W_DEAD;
+      atomicAdd(&S.sc->cnt[C_PAIRED], 1ull);
+      continue;
+    }
+    if (want_cur) atomicMin(&cur[c], key);
+  }
+  __shared__ bool last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&S.sc->ticket, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  __shared__ int more;
+  if (threadIdx.x == 0) more = 0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < ng; c += BS) {
+    if (r > 0) prev[c] = ~0ull;
+    const int k = S.kleft[c];
+    if (k <= 0) continue;
+    if (r < R && cur[c] != ~0ull) {
+      S.kleft[c] = k - 1;
+      more = 1;
+    } else {
+      atomicAdd(&S.sc->cnt[C_DEFICIT], (unsigned long long)k);
+      S.kleft[c] = 0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    S.sc->pair_active = more;
+    S.sc->ticket = 0u;
+  }
+}
+
+// ---------------------------------------------------------------- cell sort
+// Counting sort by cell, dropping dead particles.  Each thread reads GROUP
+// consecutive slots and handles runs of equal cells with one LDS atomic.
+__device__ __forceinline__ void load_w8(const int32_t *wp, int64_t i0, int32_t w[GROUP]) {
+  const int4 a = *reinterpret_cast<const int4 *>(wp + i0), b = *reinterpret_cast<const int4 *>(wp + i0 + 4);
+  w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w; w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+}
+
+template <int BS>
+__device__ void count_runs(const Sim &S, int s, int64_t N, int *cnt) {
+  const int64_t chunk = push_chunk(N, gridDim.x);
+  const int64_t begin = (int64_t)blockIdx.x * chunk, end = min(N, begin + chunk);
+  const int32_t *wp = S.p[s].w;
+  for (int64_t i0 = begin + (int64_t)GROUP * threadIdx.x; i0 < end; i0 += (int64_t)GROUP * BS) {
+    int32_t w[GROUP];
+    load_w8(wp, i0, w);
+    const int nv = (int)min((int64_t)GROUP, end - i0);
+    int rc = -1, len = 0;
+    for (int k = 0; k < nv; ++k) {
+      if (w[k] < 0) continue;
+      const int c = w[k] & (int32_t)W_CELL;
+      if (c != rc) { if (len) atomicAdd(&cnt[rc], len); rc = c; len = 0; }
+      ++len;
+    }
+    if (len) atomicAdd(&cnt[rc], len);
+  }
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_sort_count(Sim S, int s) {
+  extern __shared__ int scnt[];
+  const int ng = S.ng;
+  const int64_t N = (int64_t)S.sc->n[s];
+  for (int j = threadIdx.x; j < ng; j += BS) scnt[j] = 0;
+  __syncthreads();
+  count_runs<BS>(S, s, N, scnt);
+  __syncthreads();
+  for (int j = threadIdx.x; j < ng; j += BS)
+    if (scnt[j]) atomicAdd(&S.sortcnt[j], scnt[j]);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_sort_scan(Sim S, int s) {
+  __shared__ long long buf[BS / 64];
+  const int ng = S.ng;
+  const int per = (ng + BS - 1) / BS;
+  const int j0 = min((int)threadIdx.x * per, ng), j1 = min(j0 + per, ng);
+  long long loc = 0;
+  for (int j = j0; j < j1; ++j) loc += S.sortcnt[j];
+  long long tot;
+  long long run = block_exclusive_scan<BS, long long>(loc, buf, tot);
+  for (int j = j0; j < j1; ++j) {
+    S.sortbase[j] = (int32_t)run;
+    run += S.sortcnt[j];
+    S.sortcnt[j] = 0;
+  }
+  if (threadIdx.x == 0) {
+    S.sc->nsort[s] = S.sc->n[s];
+    S.sc->n[s] = (unsigned long long)tot;
+  }
+}
+
+// scatter into the other buffer; each block reserves one range per cell it holds
+template <int BS>
+__global__ __launch_bounds__(BS) void k_sort_scatter(Sim S, int s, Particles dst) {
+  extern __shared__ int sh_sort[];
+  int *lcnt = sh_sort, *lbase = sh_sort + S.ng;
+  const int ng = S.ng;
+  const int64_t N = (int64_t)S.sc->nsort[s];
+  const int64_t chunk = push_chunk(N, gridDim.x);
+  const int64_t begin = (int64_t)blockIdx.x * chunk, end = min(N, begin + chunk);
+  if (begin >= end) return;
+  for (int j = threadIdx.x; j < ng; j += BS) lcnt[j] = 0;
+  __syncthreads();
+  count_runs<BS>(S, s, N, lcnt);
+  __syncthreads();
+  for (int j = threadIdx.x; j < ng; j += BS) {
+    lbase[j] = lcnt[j] ? atomicAdd(&S.sortbase[j], lcnt[j]) : 0;
+    lcnt[j] = 0;
+  }
+  __syncthreads();
+  const Particles &P = S.p[s];
+  for (int64_t i0 = begin + (int64_t)GROUP * threadIdx.x; i0 < end; i0 += (int64_t)GROUP * BS) {
+    int32_t w[GROUP];
+    load_w8(P.w, i0, w);
+    const int nv = (int)min((int64_t)GROUP, end - i0);
+    int k = 0;
+    while (k < nv) {
+      if (w[k] < 0) { ++k; continue; }
+      const int c = w[k] & (int32_t)W_CELL;
+      int len = 1;
+      while (k + len < nv && w[k + len] >= 0 && (w[k + len] & (int32_t)W_CELL) == c) ++len;
+      int64_t d = (int64_t)lbase[c] + atomicAdd(&lcnt[c], len);
+      for (int m = k; m < k + len; ++m, ++d) {
+        const int64_t i = i0 + m;
+        dst.w[d] = w[m]; dst.off[d] = P.off[i]; dst.vx[d] = P.vx[i]; dst.vy[d] = P.vy[i]; dst.vz[d] = P.vz[i];
+        dst.id[d] = P.id[i];
+      }
+      k += len;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- compaction
+// Order-preserving removal of dead particles into the other buffer: per-block
+// live counts, one scan, then each block writes its live particles as one
+// contiguous range (all traffic 128-bit and coalesced).
+template <int BS>
+__global__ __launch_bounds__(BS) void k_compact_count(Sim S, int s) {
+  __shared__ long long buf[BS / 64];
+  const int64_t N = (int64_t)S.sc->n[s];
+  const int64_t chunk = push_chunk(N, gridDim.x);
+  const int64_t begin = (int64_t)blockIdx.x * chunk, end = min(N, begin + chunk);
+  long long live = 0;
+  for (int64_t i0 = begin + (int64_t)GROUP * threadIdx.x; i0 < end; i0 += (int64_t)GROUP * BS) {
+    int32_t w[GROUP];
+    load_w8(S.p[s].w, i0, w);
+    const int nv = (int)min((int64_t)GROUP, end - i0);
+    for (int k = 0; k < nv; ++k) live += w[k] >= 0;
+  }
+  long long tot;
+  block_exclusive_scan<BS, long long>(live, buf, tot);
+  if (threadIdx.x == 0) S.blkcnt[blockIdx.x] = tot;
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_compact_scan(Sim S, int s, int nblk) {
+  __shared__ long long buf[BS / 64];
+  const int per = (nblk + BS - 1) / BS;
+  const int b0 = min((int)threadIdx.x * per, nblk), b1 = min(b0 + per, nblk);
+  long long loc = 0;
+  for (int b = b0; b < b1; ++b) loc += S.blkcnt[b];
+  long long tot;
+  long long run = block_exclusive_scan<BS, long long>(loc, buf, tot);
+  for (int b = b0; b < b1; ++b) {
+    const long long c = S.blkcnt[b];
+    S.blkcnt[b] = run;
+    run += c;
+  }
+  if (threadIdx.x == 0) {
+    S.sc->nsort[s] = S.sc->n[s];
+    S.sc->n[s] = (unsigned long long)tot;
+  }
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_compact_write(Sim S, int s, Particles dst) {
+  __shared__ long long buf[BS / 64];
+  const int64_t N = (int64_t)S.sc->nsort[s];
+  const int64_t chunk = push_chunk(N, gridDim.x);
+  const int64_t begin = (int64_t)blockIdx.x * chunk, end = min(N, begin + chunk);
+  if (begin >= end) return;
+  const Particles &P = S.p[s];
+  long long out = S.blkcnt[blockIdx.x];
+  for (int64_t base = begin; base < end; base += (int64_t)GROUP * BS) {
+    const int64_t i0 = base + (int64_t)GROUP * threadIdx.x;
+    int32_t w[GROUP];
+    float off[GROUP], vx[GROUP], vy[GROUP], vz[GROUP];
+    uint32_t id[GROUP];
+    int nv = 0, live = 0;
+    if (i0 < end) {
+      nv = (int)min((int64_t)GROUP, end - i0);
+      load_w8(P.w, i0, w);
+      const float4 *o4 = reinterpret_cast<const float4 *>(P.off + i0), *x4 = reinterpret_cast<const float4 *>(P.vx + i0),
+                   *y4 = reinterpret_cast<const float4 *>(P.vy + i0), *z4 = reinterpret_cast<const float4 *>(P.vz + i0);
+      const uint4 *d4 = reinterpret_cast<const uint4 *>(P.id + i0);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float4 a = o4[h], b = x4[h], c = y4[h], d = z4[h];
+        const uint4 e = d4[h];
+        off[4 * h] = a.x; off[4 * h + 1] = a.y; off[4 * h + 2] = a.z; off[4 * h + 3] = a.w;
+        vx[4 * h] = b.x; vx[4 * h + 1] = b.y; vx[4 * h + 2] = b.z; vx[4 * h + 3] = b.w;
+        vy[4 * h] = c.x; vy[4 * h + 1] = c.y; vy[4 * h + 2] = c.z; vy[4 * h + 3] = c.w;
+        vz[4 * h] = d.x; vz[4 * h + 1] = d.y; vz[4 * h + 2] = d.z; vz[4 * h + 3] = d.w;
+        id[4 * h] = e.x; id[4 * h + 1] = e.y; id[4 * h + 2] = e.z; id[4 * h + 3] = e.w;
+      }
+      for (int k = 0; k < nv; ++k) live += w[k] >= 0;
+    }
+    long long tot;
+    long long pos = out + block_exclusive_scan<BS, long long>((long long)live, buf, tot);
+    for (int k = 0; k < nv; ++k) {
+      if (w[k] < 0) continue;
+      dst.w[pos] = w[k]; dst.off[pos] = off[k]; dst.vx[pos] = vx[k]; dst.vy[pos] = vy[k]; dst.vz[pos] = vz[k];
+      dst.id[pos] = id[k];
+      ++pos;
+    }
+    out += tot;
+  }
+}
+
+// ---------------------------------------------------------------- diagnostics
+template <int BS>
+__global__ __launch_bounds__(BS) void k_diag(Sim S, int s) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const int ng = S.ng;
+  unsigned long long *le = (unsigned long long *)dsm;
+  unsigned int *lc = (unsigned int *)(le + ng);
+  unsigned int *lb = lc + ng;
+  for (int j = threadIdx.x; j < ng; j += BS) { le[j] = 0ull; lc[j] = 0u; }
+  for (int j = threadIdx.x; j < NBIN; j += BS) lb[j] = 0u;
+  __syncthreads();
+  const Particles &P = S.p[s];
+  const int64_t N = (int64_t)S.sc->n[s];
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
+    const int32_t w = P.w[i];
+    if (w < 0) continue;
+    const float vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
+    const float e = S.half_m_e[s] * (vx * vx + vy * vy + vz * vz);
+    const int c = w & (int32_t)W_CELL;
+    atomicAdd(&le[c], (unsigned long long)__float2ll_rn(e * 1048576.0f));
+    atomicAdd(&lc[c], 1u);
+    atomicAdd(&lb[ebin(e)], 1u);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < ng; j += BS) {
+    if (lc[j]) {
+      atomicAdd(&S.esum[(size_t)s * ng + j], le[j]);
+      atomicAdd(&S.ecnt[(size_t)s * ng + j], (unsigned long long)lc[j]);
+    }
+  }
+  for (int j = threadIdx.x; j < NBIN; j += BS)
+    if (lb[j]) atomicAdd(&S.edf[(size_t)s * NBIN + j], (unsigned long long)lb[j]);
+  if (blockIdx.x == 0 && threadIdx.x == 0 && s == 0) S.nacc[1] += 1ull;
+}
+
+// ---------------------------------------------------------------- loading, leapfrog start, deposit
+template <int BS>
+__global__ __launch_bounds__(BS) void k_load(Sim S, int s, int64_t count, float vth) {
+  const Particles &P = S.p[s];
+  for (int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x; k < count; k += (int64_t)gridDim.x * BS) {
+    const uint32_t id = (uint32_t)k;
+    const U4 r0 = draw(S, s, id, 0, P_LOAD, 0);
+    const U4 r1 = draw(S, s, id, 0, P_LOAD, 1);
+    const uint64_t lat = (uint64_t)(r0.x >> 8) * (uint64_t)S.ng;     // point of the 2^24 lattice times ng
+    const int cell = (int)(lat >> 24);
+    const float off = (float)(uint32_t)(lat & 0xFFFFFFull) * 0x1p-24f;
+    float z0, z1, z2, z3;
+    normals(r1.x, r1.y, z0, z1);
+    normals(r1.z, r1.w, z2, z3);
+    const int32_t w = s == 0 ? (cell | (int32_t)new_flight(S.nd_e, r0.y)) : cell;
+    put(P, k, w, off, vth * z0, vth * z1, vth * z2);
+    P.id[k] = id;
+  }
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_shift(Sim S, int s) {
+  const Particles &P = S.p[s];
+  const int64_t N = (int64_t)S.sc->n[s];
+  const float h = -0.5f * S.qmdt[s];
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
+    const int32_t w = P.w[i];
+    if (w < 0) continue;
+    const int c = w & (int32_t)W_CELL;
+    const float off = P.off[i], e0 = S.E[c], e1 = S.E[c + 1];
+    P.vx[i] = fmaf(h, fmaf(off, e1 - e0, e0), P.vx[i]);
+  }
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_deposit(Sim S, int s) {
+  extern __shared__ unsigned long long dq[];
+  const int nn = S.ng + 1;
+  for (int j = threadIdx.x; j < nn; j += BS) dq[j] = 0ull;
+  __syncthreads();
+  const Particles &P = S.p[s];
+  const int64_t N = (int64_t)S.sc->n[s];
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
+    const int32_t w = P.w[i];
+    if (w >= 0) dep_lds(dq, w & (int32_t)W_CELL, P.off[i]);
+  }
+  __syncthreads();
+  for (int j = threadIdx.x; j < nn; j += BS)
+    if (dq[j]) atomicAdd(&S.Q[(size_t)s * nn + j], dq[j]);
+}
+
+// ---------------------------------------------------------------- launch wrappers
+constexpr int FBS = 1024;   // field / fixup / scan block
+constexpr int GBS = 256;    // grid-stride helper kernels
+
+size_t push_lds_bytes(const Sim &S, int s, int bs) {
+  const size_t nn = S.ng + 1;
+  size_t o = 0;
+  o = (o + 8 * nn + 15) & ~(size_t)15;
+  o = (o + 4 * nn + 15) & ~(size_t)15;
+  if (s == 2) o = (o + 4 * nn + 15) & ~(size_t)15;
+  o = (o + 4 * (size_t)S.nproc_sp[s] * S.ntab + 15) & ~(size_t)15;
+  if (s == 0) o = (o + 4 * (size_t)S.ntab + 15) & ~(size_t)15;
+  o += sizeof(unsigned short) * GROUP * (size_t)bs;
+  return o;
+}
+
+int max_push_grid() { return MAXGRID; }
+
+hipError_t launch_reduce(const Sim &S, int s, int push_grid, hipStream_t st) {
+  const int nn = S.ng + 1;
+  hipLaunchKernelGGL((k_reduce<256>), dim3((nn + 255) / 256, 16), dim3(256), 0, st, S, s, push_grid);
+  return hipGetLastError();
+}
+
+size_t fixup_lds_bytes(const Sim &) { return 2 * sizeof(int) * NBKT; }
+
+#define PUSH_CASE(BS_)                                                                            \
+  case BS_:                                                                                       \
+    if (s == 0) hipLaunchKernelGGL((k_push<BS_, 0>), dim3(grid), dim3(BS_), lds, st, S, step);    \
+    else if (s == 1) hipLaunchKernelGGL((k_push<BS_, 1>), dim3(grid), dim3(BS_), lds, st, S, step); \
+    else hipLaunchKernelGGL((k_push<BS_, 2>), dim3(grid), dim3(BS_), lds, st, S, step);           \
+    break;
+
+hipError_t launch_push(const Sim &S, int s, int64_t step, int grid, int block, hipStream_t st) {
+  const size_t lds = push_lds_bytes(S, s, block);
+  switch (block) {
+    PUSH_CASE(256)
+    PUSH_CASE(512)
+    PUSH_CASE(1024)
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t set_lds_limits(const Sim &S, int block) {
+  hipError_t e = hipSuccess;
+  for (int s = 0; s < NSP && e == hipSuccess; ++s) {
+    const int lds = (int)push_lds_bytes(S, s, block);
+#define SETA(BS_, S__) hipFuncSetAttribute((const void *)k_push<BS_, S__>, hipFuncAttributeMaxDynamicSharedMemorySize, lds)
+    if (block == 256) e = s == 0 ? SETA(256, 0) : s == 1 ? SETA(256, 1) : SETA(256, 2);
+    else if (block == 512) e = s == 0 ? SETA(512, 0) : s == 1 ? SETA(512, 1) : SETA(512, 2);
+    else e = s == 0 ? SETA(1024, 0) : s == 1 ? SETA(1024, 1) : SETA(1024, 2);
+#undef SETA
+  }
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_field<FBS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fixup_lds_bytes(S));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_fixup<FBS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fixup_lds_bytes(S));
+  return e;
+}
+
+hipError_t launch_field(const Sim &S, int64_t step, int mode, hipStream_t st) {
+  hipLaunchKernelGGL((k_field<FBS>), dim3(mode == 0 ? 1 + NSP : 1), dim3(FBS), fixup_lds_bytes(S), st, S, step,
+                     mode);
+  return hipGetLastError();
+}
+
+hipError_t launch_fixup(const Sim &S, hipStream_t st) {
+  hipLaunchKernelGGL((k_fixup<FBS>), dim3(NSP), dim3(FBS), fixup_lds_bytes(S), st, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_ionprep(const Sim &S, hipStream_t st) {
+  hipLaunchKernelGGL((k_ionprep<GBS>), dim3(1), dim3(GBS), 0, st, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair(const Sim &S, int64_t step, int r, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_pair<GBS>), dim3(grid), dim3(GBS), 0, st, S, step, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_sort(const Sim &S, int s, const Particles &dst, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_sort_count<GBS>), dim3(grid), dim3(GBS), sizeof(int) * S.ng, st, S, s);
+  hipLaunchKernelGGL((k_sort_scan<FBS>), dim3(1), dim3(FBS), 0, st, S, s);
+  hipLaunchKernelGGL((k_sort_scatter<GBS>), dim3(grid), dim3(GBS), 2 * sizeof(int) * S.ng, st, S, s, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact(const Sim &S, int s, const Particles &dst, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_compact_count<GBS>), dim3(grid), dim3(GBS), 0, st, S, s);
+  hipLaunchKernelGGL((k_compact_scan<FBS>), dim3(1), dim3(FBS), 0, st, S, s, grid);
+  hipLaunchKernelGGL((k_compact_write<GBS>), dim3(grid), dim3(GBS), 0, st, S, s, dst);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag(const Sim &S, int s, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_diag<GBS>), dim3(grid), dim3(GBS), (size_t)S.ng * 12 + NBIN * 4 + 16, st, S, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_load(const Sim &S, int s, int64_t count, float vth, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_load<GBS>), dim3(grid), dim3(GBS), 0, st, S, s, count, vth);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift(const Sim &S, int s, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_shift<GBS>), dim3(grid), dim3(GBS), 0, st, S, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_deposit(const Sim &S, int s, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_deposit<GBS>), dim3(grid), dim3(GBS), sizeof(unsigned long long) * (S.ng + 1), st, S, s);
+  return hipGetLastError();
+}
+
+size_t max_push_lds(const Sim &S, int block) {
+  size_t m = 0;
+  for (int s = 0; s < NSP; ++s) m = m > push_lds_bytes(S, s, block) ? m : push_lds_bytes(S, s, block);
+  return m;
+}
+
+}  // namespace picmcc

@@ -106,6 +106,7 @@ class Discharge:
     seed: int = 1
     capacity_factor: float = 4.0
     counts: Optional[tuple] = None   # explicit (e, O2+, O-) counts, if given
+    capacities: Optional[tuple] = None   # explicit slots per species, if given
 
     @property
     def dt(self) -> float:
@@ -134,11 +135,14 @@ class Discharge:
 
     def species(self) -> List[Species]:
         ce, cp, cm = self.species_counts()
-        cap = lambda c: max(1024, int(math.ceil(c * self.capacity_factor)))
+        if self.capacities is not None:
+            caps = [int(c) for c in self.capacities]
+        else:
+            caps = [max(1024, int(math.ceil(c * self.capacity_factor))) for c in (ce, cp, cm)]
         return [
-            Species(-1.0, ELECTRON_MASS, self.te0, ce, cap(ce)),
-            Species(+1.0, M_O2PLUS, self.ti0, cp, cap(cp)),
-            Species(-1.0, M_OMINUS, self.ti0, cm, cap(cm)),
+            Species(-1.0, ELECTRON_MASS, self.te0, ce, caps[0]),
+            Species(+1.0, M_O2PLUS, self.ti0, cp, caps[1]),
+            Species(-1.0, M_OMINUS, self.ti0, cm, caps[2]),
         ]
 
 
@@ -230,8 +234,8 @@ def config(i: int, **over) -> Discharge:
     elif i == 3:
         d = Discharge("cfg3-4096cells-4.8e7", L=0.04, ng=4096, U=500.0, f=13.56e6, p=100.0,
                       steps_per_cycle=2000, ksub=20, cycles=50, n_plus0=1e15, frac_minus=2.0 / 3.0,
-                      counts=(8_000_000, 24_000_000, 16_000_000), sort_every=20, diag_every=20,
-                      seed=3001, capacity_factor=1.5)
+                      counts=(8_000_000, 24_000_000, 16_000_000), sort_every=20, diag_every=100,
+                      seed=3001, capacities=(96_000_000, 96_000_000, 24_000_000))
     else:
         raise ValueError("workload index must be 1, 2 or 3 (use sweep_member for the batch)")
     return dataclasses.replace(d, **over)

@@ -1,0 +1,99 @@
+"""Shared pieces of the GPU-vs-oracle tests."""
+import math
+
+import numpy as np
+
+from oracle import pyoracle as po
+from paper_0705_0497_amd import inputs as I
+
+QE = 1.602176634e-19
+POS_TOL = 1e-5          # cells
+VEL_TOL = 1e-5          # relative to max(|v|, thermal speed of the species)
+
+
+def thermal_speed(sp):
+    return math.sqrt(max(sp.t0_ev, 0.026) * QE / sp.mass)
+
+
+def canonical_from_oracle(d, procs, seed_steps=0, species=None):
+    """Oracle-loaded state (after the leapfrog start), rounded to the FP32 record."""
+    o = po.Oracle(d, species or d.species(), procs)
+    o.load_uniform()
+    o.prepare(True)
+    if seed_steps:
+        o.step(seed_steps)
+    st = [o.canonical(s) for s in range(3)]
+    nid = [o.next_id(s) for s in range(3)]
+    return st, nid, o.step_index
+
+
+def oracle_from_canonical(d, procs, st, nid, step, species=None, **kw):
+    o = po.Oracle(d, species or d.species(), procs, **kw)
+    for s in range(3):
+        o.set_particles(s, st[s], nid[s])
+    o.set_step(step)
+    o.prepare(False)
+    return o
+
+
+def gpu_from_canonical(d, procs, st, nid, step, species=None, **kw):
+    from paper_0705_0497_amd.binding import Discharge
+    g = Discharge(d, procs, species=species, **kw)
+    for s in range(3):
+        g.set_particles(s, st[s], nid[s])
+    g.set_step(step)
+    g.prepare(False)
+    return g
+
+
+def by_id(st):
+    o = np.argsort(st["id"], kind="stable")
+    return {k: v[o] for k, v in st.items()}
+
+
+def xi_of(st):
+    if "xi" in st:
+        return st["xi"]
+    return st["cell"].astype(np.float64) + st["off"].astype(np.float64)
+
+
+def band_ids(oracle_events):
+    """(species, id) pairs whose decision fell within the 1e-6 band."""
+    ev = oracle_events
+    return set(map(tuple, ev[ev[:, 4] != 0][:, [1, 2]].tolist()))
+
+
+def compare_events(gpu_ev, orc_ev):
+    """Decisions of one step: identical outside the oracle's 1e-6 band."""
+    band = band_ids(orc_ev)
+    o = {(int(r[1]), int(r[2])): int(r[3]) for r in orc_ev if r[3] != -4}
+    g = {(int(r[1]), int(r[2])): int(r[3]) for r in gpu_ev}
+    bad = [(k, o.get(k), g.get(k)) for k in set(o) | set(g) if o.get(k) != g.get(k) and k not in band]
+    return bad, band
+
+
+def compare_states(gst, ost, sp, skip=frozenset(), s=0):
+    """Positions (cells) and velocities of matching ids; returns worst errors."""
+    g, o = by_id(gst), by_id(ost)
+    gi, oi = g["id"].astype(np.int64), o["id"].astype(np.int64)
+    keep_g = np.array([(s, int(i)) not in skip for i in gi], bool)
+    keep_o = np.array([(s, int(i)) not in skip for i in oi], bool)
+    g = {k: v[keep_g] for k, v in g.items()}
+    o = {k: v[keep_o] for k, v in o.items()}
+    assert np.array_equal(g["id"], o["id"]), "live id sets differ outside the band"
+    dx = np.abs(xi_of(g) - xi_of(o))
+    vth = thermal_speed(sp)
+    worst_v = 0.0
+    for k in ("vx", "vy", "vz"):
+        ref = np.maximum(np.abs(o[k].astype(np.float64)), vth)
+        worst_v = max(worst_v, float(np.max(np.abs(g[k].astype(np.float64) - o[k]) / ref, initial=0.0)))
+    if s == 0:
+        assert np.array_equal(g["cd"] & 0xFFFF, o["cd"] & 0xFFFF), "free-flight countdowns differ"
+    return float(np.max(dx, initial=0.0)), worst_v
+
+
+def neutralising(procs, factor=3e4):
+    for p in procs:
+        if p.kind == "neutralize":
+            p.sigma = p.sigma * factor
+    return procs
