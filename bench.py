@@ -1,10 +1,9 @@
 """Throughput of the 1D3V oxygen PIC-MCC step on one MI355X.
 
 Workload: the large single discharge (4096 cells, L = 4 cm, U = 500 V,
-p = 100 Pa, 8e6 e + 2.4e7 O2+ + 1.6e7 O-, 2000 steps per rf cycle, ions every
-20 steps, cell sort every 20 steps).  One bench "step" is one rf cycle: 2000
-electron steps with 100 ion steps, field solves, MCC, deposits, sorts and
-moments.  Inputs (seeded synthetic tables, uniform loading) are resident on the
+p = 100 Pa, 8e6 e + 2.4e7 O2+ + 1.6e7 O- loaded, 2000 steps per rf cycle, ions
+every 20 steps).  One bench "step" is one rf cycle: 2000 electron steps with 100
+ion steps, field solves, MCC, deposits, products, store re-ordering and moments.  Inputs (seeded synthetic tables, uniform loading) are resident on the
 GPU before the timed region starts.
 
 Prints one JSON line.  Roofline of the dominant kernel (electron
@@ -13,8 +12,10 @@ HIP events on the handle's stream.  cpu_baseline: the FP64 oracle on a bounded
 sample of the same workload (1/8 of the particles, 40 steps) on the host.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -29,6 +30,26 @@ HBM_PEAK_GBS = 8000.0    # MI355X HBM3E
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "push_electron_cfg3_pmc.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_0705_0497_amd", "csrc", "kernels.hip")
+
+
+def measured_traffic(particles_per_launch):
+    """HBM bytes per electron-push launch from the committed rocprofv3 --pmc
+    summary (FETCH_SIZE + WRITE_SIZE, calibrated on a plain 1 GiB copy), scaled
+    to this run's particles per launch; None when the kernel source changed since."""
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    src = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()[:16]
+    m_hash = re.search(r"kernels\.hip sha256\[:16\]:\s*([0-9a-f]{16})", text)
+    m_bpp = re.search(r"HBM bytes per electron push:\s*([0-9.]+)", text)
+    if not m_hash or not m_bpp or m_hash.group(1) != src:
+        return None
+    return float(m_bpp.group(1)) * particles_per_launch
 
 
 def cpu_baseline(d, procs):
@@ -59,6 +80,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--grid", type=int, default=0)
+    ap.add_argument("--sort", choices=("compact", "cell"), default="compact",
+                    help="periodic re-ordering: order-preserving compaction or counting sort by cell")
+    ap.add_argument("--sort-every", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs one discharge on one GPU; --gpus {args.gpus} is not supported "
@@ -68,13 +92,14 @@ def main():
     import numpy as np
     import torch
     from paper_0705_0497_amd import inputs as I
-    from paper_0705_0497_amd.binding import Discharge, C_PUSH, C_CAND, C_REDRAW, C_BORN
+    from paper_0705_0497_amd.binding import Discharge, C_PUSH, C_CAND, C_REDRAW, C_EVENT
 
     torch.cuda.set_device(0)
     d = I.config(3)
     procs = I.make_processes()
     log(f"bench: loading {d.name} ({sum(d.species_counts())} superparticles, {d.ng} cells)")
-    g = Discharge(d, procs, block=args.block, grid=args.grid)
+    g = Discharge(d, procs, block=args.block, grid=args.grid, sort_every=args.sort_every,
+                  sort_kind=1 if args.sort == "compact" else 0)
     g.load_uniform()
     g.sync()
     spc = d.steps_per_cycle
@@ -98,12 +123,16 @@ def main():
     pushes = int(dc[C_PUSH:C_PUSH + 3].sum())
     value = pushes / elapsed
     launches = args.steps * spc
+    kinds = [p.kind for p in procs]
+    ev = lambda k: sum(int(dc[C_EVENT + i]) for i, kk in enumerate(kinds) if kk == k)
+    born_in_push = 2 * ev("ionize") + ev("attach")         # products written by the electron kernel
     alg_bytes = (BYTES_PUSH * int(dc[C_PUSH]) + BYTES_CAND * int(dc[C_CAND] + dc[C_REDRAW])
-                 + BYTES_PRODUCT * int(dc[C_BORN:C_BORN + 3].sum()))
+                 + BYTES_PRODUCT * born_in_push)
     per_launch = alg_bytes / launches
     mean_ms = ms_push / launches
     achieved = per_launch / (mean_ms * 1e-3) / 1e9
     counts = [g.count(s) for s in range(3)]
+    traffic = measured_traffic(int(dc[C_PUSH]) / launches)
     out = {
         "metric": "particle-steps/s (push+deposit+MCC); rf cycles to steady state, warm vs cold",
         "value": value,
@@ -118,13 +147,14 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "4096-cell O2 CCP, L=4 cm, U=500 V, p=100 Pa, 8e6 e + 2.4e7 O2+ + 1.6e7 O-",
-                   "step": "one rf cycle = 2000 electron steps, ions every 20, sort every 20",
+                   "step": "one rf cycle = 2000 electron steps, ions every 20",
+                   "reorder": f"{args.sort} every {args.sort_every} steps",
                    "cells": d.ng, "superparticles_loaded": int(sum(d.species_counts())),
                    "superparticles_end": counts, "electron_pushes": int(dc[C_PUSH]),
                    "ion_pushes": int(dc[C_PUSH + 1] + dc[C_PUSH + 2]),
                    "electron_candidates": int(dc[C_CAND]), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_push<512,0> electron push+MCC+deposit",
                      "bytes_per_launch": per_launch, "mean_launch_ms": mean_ms},
     }

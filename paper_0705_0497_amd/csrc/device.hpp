@@ -94,7 +94,8 @@ struct Sim {
   float lnemin, invdlt, emin, emax;
   double n_o2, c_meta;
   double nd_e;                     // nu_max(e) dt
-  float nd_ef;                     // the same in FP32
+  float inv_nd_ef;                 // 1 / (nu_max(e) dt) in FP32, 0 if nu_max = 0
+  float invdlt2, l2emin_s;         // table index t = log2(E) invdlt2 - l2emin_s
   const float *ttot_e;             // [ntab] sum over electron processes of scale_p sigma_p
   unsigned long long *part;        // [grid][ng+1] per-block charge partials
   long long *blkcnt;               // [grid] live counts / output offsets of the compaction

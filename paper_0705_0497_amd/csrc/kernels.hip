@@ -24,10 +24,10 @@ __device__ __forceinline__ U4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r) { k0 += 0x9E3779B9u; k1 += 0xBB67AE85u; }
-    const uint32_t lo0 = 0xD2511F53u * c0, hi0 = __umulhi(0xD2511F53u, c0);
-    const uint32_t lo1 = 0xCD9E8D57u * c2, hi1 = __umulhi(0xCD9E8D57u, c2);
-    const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;   // one 32x32->64 product each
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c0 = n0; c1 = (uint32_t)p1; c2 = n2; c3 = (uint32_t)p0;
   }
   return {c0, c1, c2, c3};
 }
@@ -72,7 +72,7 @@ __device__ __forceinline__ uint32_t new_flight(double nd, uint32_t x) {
 struct TabPos { int i; float w; };
 
 __device__ __forceinline__ TabPos tab_pos(const Sim &S, float ec) {
-  float t = (logf(ec) - S.lnemin) * S.invdlt;
+  float t = fmaf(__log2f(ec), S.invdlt2, -S.l2emin_s);   // (log2 E - log2 Emin) / step in log2
   t = fminf(fmaxf(t, 0.0f), (float)(S.ntab - 1));
   const int i = min((int)t, S.ntab - 2);
   return {i, t - (float)i};
@@ -350,6 +350,10 @@ __global__ __launch_bounds__(BS) void k_fixup(Sim S) {
 // histogram, so no global atomics are needed for the bulk of the charge.
 constexpr int GROUP = 8;
 constexpr int MAXGRID = 2048;
+#ifndef PICMCC_CAND_ILP
+#define PICMCC_CAND_ILP 1
+#endif
+constexpr int CAND_ILP = PICMCC_CAND_ILP;   // candidates whose gathers a thread keeps in flight
 
 // energies of particles absorbed at x = 0 / x = L, per block
 struct WallHist { unsigned int iedf[2][NBIN]; };
@@ -366,6 +370,9 @@ struct PushShared {
 __device__ __forceinline__ size_t align_up(size_t x) { return (x + 15) & ~(size_t)15; }
 
 struct BlockCounts { unsigned int c[NCOUNT]; };
+
+// per-thread tallies of the frequent outcomes, added to the block counters once
+struct ThreadCounts { unsigned int push = 0u, cand = 0u, nul = 0u; };
 
 // adds the number of active lanes to one block counter with a single LDS atomic
 __device__ __forceinline__ void count_lanes(BlockCounts &bc, int idx) {
@@ -398,22 +405,34 @@ __device__ __forceinline__ void emit(const Sim &S, int s, int ps, uint32_t pid, 
 }
 
 // free flight in steps from an FP32 draw (the 1e-6 decision band covers FP32)
-__device__ __forceinline__ uint32_t new_flight_f(float ndf, uint32_t x) {
-  const float tau = ndf > 0.0f ? -logf(unif(x)) / ndf : (float)CD_MAX;
+__device__ __forceinline__ uint32_t new_flight_f(float inv_nd, uint32_t x) {
+  // tau = -ln u / (nu_max dt); inv_nd = 1 / (nu_max dt) (0 when nothing collides)
+  const float tau = inv_nd > 0.0f ? -__log2f(unif(x)) * (0.69314718055994531f * inv_nd) : (float)CD_MAX;
   if (!(tau < (float)CD_MAX)) return ((uint32_t)CD_MAX << W_CD_SHIFT) | W_CAP;
   return (uint32_t)(1 + (int)tau) << W_CD_SHIFT;
 }
 
-// electron collision at the end of a free flight; the post-push state is in memory
-__device__ void collide_electron(const Sim &S, int64_t step, int64_t i, PushShared sh, BlockCounts &bc) {
+// state of a collision candidate, gathered before any of it is used
+struct Cand { int64_t i; int32_t w; uint32_t id; float off, vx, vy, vz; };
+
+__device__ __forceinline__ Cand load_cand(const Particles &P, int64_t i) {
+  Cand c;
+  c.i = i; c.w = P.w[i]; c.id = P.id[i]; c.off = P.off[i]; c.vx = P.vx[i]; c.vy = P.vy[i]; c.vz = P.vz[i];
+  return c;
+}
+
+// electron collision at the end of a free flight (post-push state in q)
+__device__ void collide_electron(const Sim &S, int64_t step, const Cand &q, PushShared sh, BlockCounts &bc,
+                                 ThreadCounts &tc) {
   const Particles &P = S.p[0];
-  const int32_t w = P.w[i];
-  const float off = P.off[i];
-  const uint32_t id = P.id[i];
-  float vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
+  const int64_t i = q.i;
+  const int32_t w = q.w;
+  const float off = q.off;
+  const uint32_t id = q.id;
+  const float vx = q.vx, vy = q.vy, vz = q.vz;
   const int cell = w & (int32_t)W_CELL;
   const U4 c = draw(S, 0, id, step, P_CAND, 0);
-  const uint32_t flight = new_flight_f(S.nd_ef, c.x);
+  const uint32_t flight = new_flight_f(S.inv_nd_ef, c.x);
   if (w & (int32_t)W_CAP) {                    // capped flight: redraw, no collision
     P.w[i] = cell | (int32_t)flight;
     dep_lds(sh.Q, cell, off);
@@ -421,7 +440,7 @@ __device__ void collide_electron(const Sim &S, int64_t step, int64_t i, PushShar
     log_event(S, step, 0, id, -2);
     return;
   }
-  count_lanes(bc, C_CAND + 0);
+  ++tc.cand;
   const float v2 = vx * vx + vy * vy + vz * vz;
   const float e = S.half_m_e[0] * v2;
   float ec = e;
@@ -450,7 +469,7 @@ __device__ void collide_electron(const Sim &S, int64_t step, int64_t i, PushShar
   if (chosen < 0) {
     P.w[i] = cell | (int32_t)flight;
     dep_lds(sh.Q, cell, off);
-    count_lanes(bc, C_NULL + 0);
+    ++tc.nul;
     return;
   }
   atomicAdd(&bc.c[C_EVENT + chosen], 1u);
@@ -472,7 +491,7 @@ __device__ void collide_electron(const Sim &S, int64_t step, int64_t i, PushShar
       float s0, s1, s2;
       iso_dir(p0.y, p0.z, s0, s1, s2);
       const float vm = sqrtf(S.two_e_m[0] * fmaxf(r * er, 0.0f));
-      emit(S, 0, 0, id, cell | (int32_t)new_flight_f(S.nd_ef, p0.w), off, vm * s0, vm * s1, vm * s2);
+      emit(S, 0, 0, id, cell | (int32_t)new_flight_f(S.inv_nd_ef, p0.w), off, vm * s0, vm * s1, vm * s2);
       dep_lds(sh.Q, cell, off);
       count_lanes(bc, C_BORN + 0);
     }
@@ -508,15 +527,16 @@ __device__ void collide_electron(const Sim &S, int64_t step, int64_t i, PushShar
 // ion collision candidate: O2+ charge exchange; O- neutralisation against the
 // O2+ grid density or associative detachment on O2(a), Eq. (1)
 template <int S_>
-__device__ void collide_ion(const Sim &S, int64_t step, int64_t i, PushShared sh, BlockCounts &bc,
-                            float inv_numax) {
+__device__ void collide_ion(const Sim &S, int64_t step, const Cand &q, PushShared sh, BlockCounts &bc,
+                            ThreadCounts &tc, float inv_numax) {
   const Particles &P = S.p[S_];
-  const int32_t w = P.w[i];
-  const float off = P.off[i];
-  const uint32_t id = P.id[i];
-  const float vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
+  const int64_t i = q.i;
+  const int32_t w = q.w;
+  const float off = q.off;
+  const uint32_t id = q.id;
+  const float vx = q.vx, vy = q.vy, vz = q.vz;
   const int cell = w & (int32_t)W_CELL;
-  count_lanes(bc, C_CAND + S_);
+  ++tc.cand;
   const U4 c = draw(S, S_, id, step, P_CAND, 0);
   const U4 t = draw(S, S_, id, step, P_TARGET, 0);
   float z0, z1, z2, z3;
@@ -551,7 +571,7 @@ __device__ void collide_ion(const Sim &S, int64_t step, int64_t i, PushShared sh
   if (chosen < 0) {
     P.w[i] = cell;
     dep_lds(sh.Q, cell, off);
-    count_lanes(bc, C_NULL + S_);
+    ++tc.nul;
     return;
   }
   atomicAdd(&bc.c[C_EVENT + chosen], 1u);
@@ -568,7 +588,7 @@ __device__ void collide_ion(const Sim &S, int64_t step, int64_t i, PushShared sh
     float d0, d1, d2;
     iso_dir(p0.y, p0.z, d0, d1, d2);
     const float vm = sqrtf(S.two_e_m[0] * erel_c);
-    emit(S, 0, S_, id, cell | (int32_t)new_flight_f(S.nd_ef, p0.w), off, vm * d0, vm * d1, vm * d2);
+    emit(S, 0, S_, id, cell | (int32_t)new_flight_f(S.inv_nd_ef, p0.w), off, vm * d0, vm * d1, vm * d2);
     dep_global(S.Q, cell, off);
     count_lanes(bc, C_BORN + 0);
     P.w[i] = W_DEAD;
@@ -580,8 +600,11 @@ __device__ __forceinline__ int64_t push_chunk(int64_t N, int grid) {
   return (chunk + GROUP - 1) / GROUP * GROUP;
 }
 
+#ifndef PICMCC_PUSH_WAVES
+#define PICMCC_PUSH_WAVES 1
+#endif
 template <int BS, int S_>
-__global__ __launch_bounds__(BS) void k_push(Sim S, int64_t step) {
+__global__ __launch_bounds__(BS, PICMCC_PUSH_WAVES) void k_push(Sim S, int64_t step) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ int qn[2];
   __shared__ BlockCounts bc;
@@ -623,7 +646,7 @@ __global__ __launch_bounds__(BS) void k_push(Sim S, int64_t step) {
   const float qmdt = S.qmdt[S_], dtdx = S.dtdx[S_];
   const bool nocoll = (S.flags & F_NO_COLL) != 0;
   const int lane = threadIdx.x & 63;
-  unsigned int npush = 0;
+  ThreadCounts tc;
   DepRun run;
   int par = 0;
   for (int64_t base = begin; base < end; base += (int64_t)GROUP * BS, par ^= 1) {
@@ -649,7 +672,7 @@ __global__ __launch_bounds__(BS) void k_push(Sim S, int64_t step) {
 #pragma unroll
       for (int k = 0; k < GROUP; ++k) {
         if (k >= nv || w[k] < 0) continue;
-        ++npush;
+        ++tc.push;
         const int cell = w[k] & (int32_t)W_CELL;
         // gather (linear weighting), leapfrog velocity then position
         const float e0 = sh.E[cell], e1 = sh.E[cell + 1];
@@ -712,14 +735,28 @@ __global__ __launch_bounds__(BS) void k_push(Sim S, int64_t step) {
     __syncthreads();
     const int nq = qn[par];
     if (threadIdx.x == 0) qn[par ^ 1] = 0;     // counter of the next pass, unused since the last barrier
-    for (int k = threadIdx.x; k < nq; k += BS) {
-      if (S_ == 0) collide_electron(S, step, base + sh.queue[k], sh, bc);
-      else collide_ion<S_>(S, step, base + sh.queue[k], sh, bc, inv_numax);
+    for (int k = threadIdx.x; k < nq; k += CAND_ILP * BS) {
+      // gathers of up to CAND_ILP candidates in flight together
+      Cand c[CAND_ILP];
+      bool h[CAND_ILP];
+#pragma unroll
+      for (int u = 0; u < CAND_ILP; ++u) {
+        h[u] = k + u * BS < nq;
+        if (h[u]) c[u] = load_cand(P, base + sh.queue[k + u * BS]);
+      }
+#pragma unroll
+      for (int u = 0; u < CAND_ILP; ++u) {
+        if (!h[u]) continue;
+        if (S_ == 0) collide_electron(S, step, c[u], sh, bc, tc);
+        else collide_ion<S_>(S, step, c[u], sh, bc, tc, inv_numax);
+      }
     }
     __syncthreads();
   }
   run.flush(sh.Q);
-  atomicAdd(&bc.c[C_PUSH + S_], npush);
+  atomicAdd(&bc.c[C_PUSH + S_], tc.push);
+  if (tc.cand) atomicAdd(&bc.c[C_CAND + S_], tc.cand);
+  if (tc.nul) atomicAdd(&bc.c[C_NULL + S_], tc.nul);
   __syncthreads();
   unsigned long long *part = S.part + (size_t)blockIdx.x * nn;
   for (int j = threadIdx.x; j < nn; j += BS) part[j] = sh.Q[j];

@@ -325,6 +325,11 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
   S.ntab = c.table_n;
   S.lnemin = (float)std::log(c.table_emin);
   S.invdlt = (float)((double)(c.table_n - 1) / (std::log(c.table_emax) - std::log(c.table_emin)));
+  {
+    const double inv2 = (double)(c.table_n - 1) / (std::log2(c.table_emax) - std::log2(c.table_emin));
+    S.invdlt2 = (float)inv2;
+    S.l2emin_s = (float)(std::log2(c.table_emin) * inv2);
+  }
   S.emin = (float)c.table_emin;
   S.emax = (float)c.table_emax;
   for (int s = 0; s < NSP; ++s) {
@@ -348,7 +353,7 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
   h->numax[0] = nu_bound(h, 0, n_o2);
   h->numax[1] = nu_bound(h, 1, n_o2);
   S.nd_e = h->numax[0] * dt;
-  S.nd_ef = (float)S.nd_e;
+  S.inv_nd_ef = S.nd_e > 0.0 ? (float)(1.0 / S.nd_e) : 0.0f;
   S.pnull_pos = 1.0 - std::exp(-h->numax[1] * dti);
   for (int p = 0; p < nproc; ++p) {
     const pic_process &P = h->pr[p];
