@@ -228,6 +228,86 @@ int pic_step_timed(pic_handle *h, int64_t n_steps, double *ms_push_e, double *ms
 const char *pic_strerror(int code);
 const char *pic_last_error(const pic_handle *h);
 
+/* ------------------------------------------------------------------ batches
+   Many discharges (different gaps, cells, voltages, pressures, particle counts,
+   tables) advanced together.  Every kernel of a step is ONE launch over all
+   members: the particle push is a persistent launch over a list of tiles cut
+   from every member's store, the field solves and product-id assignments run
+   as one block group per member.  One rf cycle of launches is captured once as
+   a HIP graph and replayed; the step index each kernel uses is a per-member
+   device counter advanced at the end of every cycle.
+
+   The members are ordinary handles made by pic_create on the batch's stream;
+   the batch does not own them and they must outlive it.  A member advanced in
+   a batch reaches the same state as the same handle advanced alone by
+   pic_step: the random streams are keyed by the member's own seed, and block
+   size, grid and re-ordering interval change the storage order only.
+
+   pic_batch_create checks: 1..64 distinct members created on `stream`, equal
+   steps_per_cycle, every member's ksub and diag_every (if > 0) divide
+   steps_per_cycle, member grid 0.  Between pic_batch_step_cycles /
+   pic_batch_autotune and pic_batch_sync the members' own calls return
+   PIC_EBUSY.  Member step indices must be multiples of steps_per_cycle when
+   a batch call starts. */
+#define PIC_EBUSY (-8)         /* member of a batch with unsynchronised work */
+
+typedef struct pic_batch pic_batch;
+
+typedef struct pic_batch_config {
+  int32_t block;           /* threads per block of the batched push: 256, 512 or 1024 (0 = 512) */
+  int32_t sort_every;      /* compaction of all members every sort_every steps (0 = never);
+                              must divide steps_per_cycle */
+  int32_t use_graph;       /* != 0: replay one captured rf cycle (needs a non-NULL stream) */
+  int32_t grid;            /* blocks of the batched push (0 = all resident blocks), <= 2048 */
+} pic_batch_config;
+
+#define PIC_TUNE_MAX 32
+typedef struct pic_batch_tuning {
+  int32_t n;                        /* candidates timed */
+  int32_t block[PIC_TUNE_MAX];
+  int32_t sort_every[PIC_TUNE_MAX];
+  double ms_per_step[PIC_TUNE_MAX]; /* device time per step of the trial window */
+  int32_t best;                     /* index of the candidate now configured */
+} pic_batch_tuning;
+
+/* Device bytes of a batch of n_members (Sim records and counters). */
+int pic_batch_query(int32_t n_members, uint64_t *workspace_bytes);
+
+/* `workspace`: caller-owned device memory of at least pic_batch_query bytes. */
+int pic_batch_create(pic_handle *const *members, int32_t n_members, const pic_batch_config *cfg,
+                     void *workspace, uint64_t workspace_bytes, void *stream, pic_batch **out);
+
+/* Advances every member by `cycles` rf cycles (steps_per_cycle steps each).
+   Asynchronous: replays the cycle graph, or enqueues the launches directly. */
+int pic_batch_step_cycles(pic_batch *b, int64_t cycles);
+
+/* Waits for the stream, hands the members back (their particle buffers and
+   step index) and reports the first member's sticky device error. */
+int pic_batch_sync(pic_batch *b);
+
+/* Changes block, grid, re-ordering interval or graph use (drops the graph). */
+int pic_batch_set_config(pic_batch *b, const pic_batch_config *cfg);
+int pic_batch_get_config(const pic_batch *b, pic_batch_config *cfg);
+
+/* Autotuner: times every (block, sort_every) candidate over `window` steps of
+   the running batch (block in {256, 512, 1024}; sort_every among 10, 20, 50,
+   100, 200, 500, 1000 dividing both window and steps_per_cycle), configures the
+   fastest, then completes the rf cycle so the members end on a cycle boundary.
+   The trial steps are real steps of the members.  Synchronises. */
+int pic_batch_autotune(pic_batch *b, int32_t window, pic_batch_tuning *out);
+
+int pic_batch_destroy(pic_batch *b);
+const char *pic_batch_last_error(const pic_batch *b);
+
+/* Largest ion subcycling factor k dividing steps_per_cycle with
+   (i) omega_pi k dt <= 0.2 for both ion species at ion density n_ion_max [m^-3]
+   (leapfrog accuracy well inside its stability limit 2), and
+   (ii) an ion that fell through the potential phi_max [V] moves at most one cell
+   per ion step (CIC field of every crossed cell seen).  Pure host call; *ksub = 1
+   when even k = 1 violates them. */
+int pic_ksub_select(const pic_config *cfg, const pic_species *sp /* [3] */, double n_ion_max,
+                    double phi_max, int32_t *ksub);
+
 #ifdef __cplusplus
 }
 #endif

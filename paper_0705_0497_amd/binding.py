@@ -16,6 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpicmcc.so")
 
 PIC_OK, PIC_EINVAL, PIC_ECAPACITY, PIC_EIDOVERFLOW, PIC_ENAN, PIC_EHIP, PIC_ENODEVICE = 0, -1, -2, -3, -5, -6, -7
+PIC_EBUSY = -8
+TUNE_MAX = 32
 KIND = {"elastic": 0, "excite": 1, "ionize": 2, "attach": 3, "cx": 4, "neutralize": 5, "detach": 6}
 TARGET = {"O2": 0, "O2a": 1, "grid+": 2}
 F_EXT_FIELD, F_NO_COLL = 1, 2
@@ -26,7 +28,10 @@ C_PAIRED, C_DEFICIT, C_CLAMP, C_REDRAW = 34, 35, 36, 37
 EXPORTS = ("pic_version", "pic_query", "pic_create", "pic_destroy", "pic_load_uniform", "pic_set_particles",
            "pic_count", "pic_get_particles", "pic_prepare", "pic_set_step", "pic_get_step", "pic_step",
            "pic_sync", "pic_moments", "pic_get_hist", "pic_get_field", "pic_get_counters", "pic_get_events",
-           "pic_nu_max", "pic_step_timed", "pic_strerror", "pic_last_error")
+           "pic_nu_max", "pic_step_timed", "pic_strerror", "pic_last_error",
+           "pic_batch_query", "pic_batch_create", "pic_batch_step_cycles", "pic_batch_sync",
+           "pic_batch_set_config", "pic_batch_get_config", "pic_batch_autotune", "pic_batch_destroy",
+           "pic_batch_last_error", "pic_ksub_select")
 
 
 class PicError(RuntimeError):
@@ -59,6 +64,15 @@ class pic_process(C.Structure):
 class pic_moments_out(C.Structure):
     _fields_ = [("sum_q", C.c_void_p), ("sum_phi", C.c_void_p), ("esum", C.c_void_p), ("ecnt", C.c_void_p),
                 ("edf", C.c_void_p), ("iedf", C.c_void_p), ("nacc", C.c_int64), ("ndiag", C.c_int64)]
+
+
+class pic_batch_config(C.Structure):
+    _fields_ = [("block", C.c_int32), ("sort_every", C.c_int32), ("use_graph", C.c_int32), ("grid", C.c_int32)]
+
+
+class pic_batch_tuning(C.Structure):
+    _fields_ = [("n", C.c_int32), ("block", C.c_int32 * TUNE_MAX), ("sort_every", C.c_int32 * TUNE_MAX),
+                ("ms_per_step", C.c_double * TUNE_MAX), ("best", C.c_int32)]
 
 
 _lib = None
@@ -97,6 +111,17 @@ def lib():
         L.pic_strerror.argtypes = [i32]
         L.pic_last_error.restype = C.c_char_p
         L.pic_last_error.argtypes = [vp]
+        L.pic_batch_query.argtypes = [i32, P(C.c_uint64)]
+        L.pic_batch_create.argtypes = [P(vp), i32, P(pic_batch_config), vp, C.c_uint64, vp, P(vp)]
+        L.pic_batch_step_cycles.argtypes = [vp, i64]
+        L.pic_batch_sync.argtypes = [vp]
+        L.pic_batch_set_config.argtypes = [vp, P(pic_batch_config)]
+        L.pic_batch_get_config.argtypes = [vp, P(pic_batch_config)]
+        L.pic_batch_autotune.argtypes = [vp, i32, P(pic_batch_tuning)]
+        L.pic_batch_destroy.argtypes = [vp]
+        L.pic_batch_last_error.restype = C.c_char_p
+        L.pic_batch_last_error.argtypes = [vp]
+        L.pic_ksub_select.argtypes = [P(pic_config), P(pic_species), dbl, dbl, P(i32)]
         _lib = L
     return _lib
 
@@ -104,6 +129,12 @@ def lib():
 def _check(code, h=None):
     if code != PIC_OK:
         msg = lib().pic_last_error(h).decode() or lib().pic_strerror(code).decode()
+        raise PicError(code, msg)
+
+
+def _bcheck(code, b=None):
+    if code != PIC_OK:
+        msg = lib().pic_batch_last_error(b).decode() or lib().pic_strerror(code).decode()
         raise PicError(code, msg)
 
 
@@ -356,3 +387,107 @@ class Discharge:
 
     def step_timed(self, n):
         return pic_step_timed(self.h, n)
+
+
+# ---------------------------------------------------------------- batches, same names
+def pic_batch_query(n_members):
+    n = C.c_uint64(0)
+    _bcheck(lib().pic_batch_query(int(n_members), C.byref(n)))
+    return n.value
+
+
+def pic_batch_create(handles, cfg, workspace_ptr, nbytes, stream_ptr):
+    arr = (C.c_void_p * len(handles))(*[h.value if isinstance(h, C.c_void_p) else h for h in handles])
+    b = C.c_void_p()
+    _bcheck(lib().pic_batch_create(arr, len(handles), C.byref(cfg), C.c_void_p(workspace_ptr), nbytes,
+                                   C.c_void_p(stream_ptr), C.byref(b)))
+    return b
+
+
+def pic_batch_step_cycles(b, cycles):
+    _bcheck(lib().pic_batch_step_cycles(b, int(cycles)), b)
+
+
+def pic_batch_sync(b):
+    _bcheck(lib().pic_batch_sync(b), b)
+
+
+def pic_batch_set_config(b, cfg):
+    _bcheck(lib().pic_batch_set_config(b, C.byref(cfg)), b)
+
+
+def pic_batch_get_config(b):
+    c = pic_batch_config()
+    _bcheck(lib().pic_batch_get_config(b, C.byref(c)), b)
+    return c
+
+
+def pic_batch_autotune(b, window):
+    t = pic_batch_tuning()
+    _bcheck(lib().pic_batch_autotune(b, int(window), C.byref(t)), b)
+    return t
+
+
+def pic_batch_destroy(b):
+    _bcheck(lib().pic_batch_destroy(b))
+
+
+def pic_ksub_select(cfg, sp, n_ion_max, phi_max):
+    k = C.c_int32(0)
+    _check(lib().pic_ksub_select(C.byref(cfg), sp, float(n_ion_max), float(phi_max), C.byref(k)))
+    return k.value
+
+
+class Batch:
+    """Discharges advanced together (one launch per kernel per step, one HIP
+    graph per rf cycle).  `members` are Discharge objects created on one
+    non-default stream; they are handed back by sync()."""
+
+    def __init__(self, members, block=0, sort_every=20, use_graph=True, grid=0):
+        import torch
+        self.members = list(members)
+        self.stream = self.members[0].stream
+        nbytes = pic_batch_query(len(self.members))
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.cfg = pic_batch_config(block, sort_every, 1 if use_graph else 0, grid)
+        self.b = pic_batch_create([m.h for m in self.members], self.cfg, self.workspace.data_ptr(), nbytes,
+                                  self.stream.cuda_stream)
+
+    def step_cycles(self, n=1):
+        pic_batch_step_cycles(self.b, n)
+
+    def sync(self):
+        pic_batch_sync(self.b)
+
+    def config(self):
+        c = pic_batch_get_config(self.b)
+        return {"block": c.block, "sort_every": c.sort_every, "use_graph": bool(c.use_graph), "grid": c.grid}
+
+    def set_config(self, block=None, sort_every=None, use_graph=None, grid=None):
+        c = pic_batch_get_config(self.b)
+        if block is not None:
+            c.block = block
+        if sort_every is not None:
+            c.sort_every = sort_every
+        if use_graph is not None:
+            c.use_graph = 1 if use_graph else 0
+        if grid is not None:
+            c.grid = grid
+        pic_batch_set_config(self.b, c)
+
+    def autotune(self, window=200):
+        t = pic_batch_autotune(self.b, window)
+        trials = [{"block": t.block[i], "sort_every": t.sort_every[i], "ms_per_step": t.ms_per_step[i]}
+                  for i in range(t.n)]
+        return {"trials": trials, "best": trials[t.best] if t.n else None}
+
+    def close(self):
+        if getattr(self, "b", None):
+            pic_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -14,7 +14,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # packed-FP32 instructions are switched off for every gfx950 code object
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-ffp-contract=fast", "-fno-hip-fp32-correctly-rounded-divide-sqrt"]
+         "-ffp-contract=on", "-fno-hip-fp32-correctly-rounded-divide-sqrt"]
 
 
 def build(verbose: bool = False) -> str:

@@ -73,6 +73,7 @@ struct Sim {
   uint64_t seed;
   // species
   Particles p[NSP];
+  Particles alt[NSP];              // the other buffer of each species (batched re-ordering)
   uint64_t *pkey[NSP];             // (parent species, parent id, local index) of this step's products
   int32_t *pbkt[NSP];              // bucket of each product's parent key
   uint64_t *ptmp[NSP];             // keys grouped by bucket during the id assignment
@@ -118,6 +119,27 @@ struct Sim {
   long long *events;
   int64_t event_cap;
   int32_t pair_rounds;
+};
+
+// device state of a batch of discharges advanced together
+constexpr int MAXBATCH = 64;
+constexpr int CBLK = 1024;         // compaction blocks per species in a batch (blkcnt stride)
+struct BatchDev {
+  int64_t base[MAXBATCH];          // step of each member when the running cycle began
+  int32_t rows[NSP][MAXBATCH];     // partial-histogram rows written by the last batched push
+};
+
+// launch shapes of a batch (host side)
+struct BatchLaunch {
+  Sim *sims;                       // device array [nmem]
+  BatchDev *bd;
+  int nmem;
+  int block;                       // push block size
+  int push_grid[NSP];              // persistent push grid per species
+  size_t push_lds[NSP];            // largest member LDS per species
+  int nn_max;                      // largest ng + 1
+  size_t diag_lds;
+  int cgrid, pgrid, dgrid;         // compaction / pairing / diagnostics blocks per member
 };
 
 }  // namespace picmcc

@@ -603,18 +603,22 @@ __device__ __forceinline__ int64_t push_chunk(int64_t N, int grid) {
 #ifndef PICMCC_PUSH_WAVES
 #define PICMCC_PUSH_WAVES 1
 #endif
+// block-level LDS state of a push run besides the dynamic part
+struct PushLds {
+  int qn[2];
+  BlockCounts bc;
+  WallHist wall;
+};
+
+// Push of the slots [begin, end) of species S_ by one block (begin a multiple of
+// GROUP).  The block's charge histogram is written to part_row (ng + 1 entries).
 template <int BS, int S_>
-__global__ __launch_bounds__(BS, PICMCC_PUSH_WAVES) void k_push(Sim S, int64_t step) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ int qn[2];
-  __shared__ BlockCounts bc;
-  __shared__ WallHist wall;
+__device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t begin, int64_t end,
+                                         unsigned long long *part_row, unsigned char *smem, PushLds &pl) {
+  int *qn = pl.qn;
+  BlockCounts &bc = pl.bc;
+  WallHist &wall = pl.wall;
   const int ng = S.ng, nn = ng + 1;
-  const int64_t N = (int64_t)S.sc->n[S_];
-  const int64_t chunk = push_chunk(N, gridDim.x);
-  const int64_t begin = (int64_t)blockIdx.x * chunk;
-  const int64_t end = min(N, begin + chunk);
-  if (begin >= end) return;
   const int np = S.nproc_sp[S_];
   PushShared sh;
   size_t o = 0;
@@ -758,13 +762,26 @@ __global__ __launch_bounds__(BS, PICMCC_PUSH_WAVES) void k_push(Sim S, int64_t s
   if (tc.cand) atomicAdd(&bc.c[C_CAND + S_], tc.cand);
   if (tc.nul) atomicAdd(&bc.c[C_NULL + S_], tc.nul);
   __syncthreads();
-  unsigned long long *part = S.part + (size_t)blockIdx.x * nn;
-  for (int j = threadIdx.x; j < nn; j += BS) part[j] = sh.Q[j];
+  for (int j = threadIdx.x; j < nn; j += BS) part_row[j] = sh.Q[j];
   for (int j = threadIdx.x; j < 2 * NBIN; j += BS)
     if (wall.iedf[j / NBIN][j % NBIN])
       atomicAdd(&S.iedf[(size_t)S_ * 2 * NBIN + j], (unsigned long long)wall.iedf[j / NBIN][j % NBIN]);
   for (int k = threadIdx.x; k < NCOUNT; k += BS)
     if (bc.c[k]) atomicAdd(&S.sc->cnt[k], (unsigned long long)bc.c[k]);
+  __syncthreads();   // the LDS may be set up for the next run
+}
+
+// one discharge: block b pushes the b-th contiguous chunk of the store
+template <int BS, int S_>
+__global__ __launch_bounds__(BS, PICMCC_PUSH_WAVES) void k_push(Sim S, int64_t step) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ PushLds pl;
+  const int64_t N = (int64_t)S.sc->n[S_];
+  const int64_t chunk = push_chunk(N, gridDim.x);
+  const int64_t begin = (int64_t)blockIdx.x * chunk;
+  const int64_t end = min(N, begin + chunk);
+  if (begin >= end) return;
+  push_run<BS, S_>(S, step, begin, end, S.part + (size_t)blockIdx.x * (S.ng + 1), smem, pl);
 }
 
 // Q[s] += sum of the partial histograms of the blocks that had particles
@@ -784,7 +801,7 @@ __global__ __launch_bounds__(BS) void k_reduce(Sim S, int s, int push_grid) {
 // O- bound of this ion step: nu_max = max_k sum_p n_p H_p[k], with n = the
 // largest O2+ node density for neutralisation and C n(O2) for detachment
 template <int BS>
-__global__ __launch_bounds__(BS) void k_ionprep(Sim S) {
+__device__ void ionprep_block(const Sim &S) {
   __shared__ double red[BS];
   const int ng = S.ng, nn = ng + 1;
   double nmax = 0.0;
@@ -827,12 +844,15 @@ __global__ __launch_bounds__(BS) void k_ionprep(Sim S) {
   }
 }
 
+template <int BS>
+__global__ __launch_bounds__(BS) void k_ionprep(Sim S) { ionprep_block<BS>(S); }
+
 // Pairing round r of an ion step.  Every neutralised O- in cell j removes one
 // pre-step O2+ of cell j: round r removes the winner of round r-1 (smallest key
 // (pairing draw, id) among the O2+ left in the cell) and finds the next minimum.
 // The last block to finish settles the per-cell bookkeeping.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_pair(Sim S, int64_t step, int r) {
+__device__ void pair_block(const Sim &S, int64_t step, int r) {
   if (!S.sc->pair_active) return;
   const int ng = S.ng, nn = ng + 1, R = S.pair_rounds;
   unsigned long long *cur = S.cmin + (size_t)(r & 1) * ng;
@@ -888,6 +908,9 @@ __global__ __launch_bounds__(BS) void k_pair(Sim S, int64_t step, int r) {
     S.sc->ticket = 0u;
   }
 }
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_pair(Sim S, int64_t step, int r) { pair_block<BS>(S, step, r); }
 
 // ---------------------------------------------------------------- cell sort
 // Counting sort by cell, dropping dead particles.  Each thread reads GROUP
@@ -997,52 +1020,50 @@ __global__ __launch_bounds__(BS) void k_sort_scatter(Sim S, int s, Particles dst
 // live counts, one scan, then each block writes its live particles as one
 // contiguous range (all traffic 128-bit and coalesced).
 template <int BS>
-__global__ __launch_bounds__(BS) void k_compact_count(Sim S, int s) {
+__device__ void compact_count_block(const Particles &P, int64_t N, long long *blk) {
   __shared__ long long buf[BS / 64];
-  const int64_t N = (int64_t)S.sc->n[s];
   const int64_t chunk = push_chunk(N, gridDim.x);
   const int64_t begin = (int64_t)blockIdx.x * chunk, end = min(N, begin + chunk);
   long long live = 0;
   for (int64_t i0 = begin + (int64_t)GROUP * threadIdx.x; i0 < end; i0 += (int64_t)GROUP * BS) {
     int32_t w[GROUP];
-    load_w8(S.p[s].w, i0, w);
+    load_w8(P.w, i0, w);
     const int nv = (int)min((int64_t)GROUP, end - i0);
     for (int k = 0; k < nv; ++k) live += w[k] >= 0;
   }
   long long tot;
   block_exclusive_scan<BS, long long>(live, buf, tot);
-  if (threadIdx.x == 0) S.blkcnt[blockIdx.x] = tot;
+  if (threadIdx.x == 0) blk[blockIdx.x] = tot;
 }
 
+// block live counts -> output offsets; the species count becomes the live count
 template <int BS>
-__global__ __launch_bounds__(BS) void k_compact_scan(Sim S, int s, int nblk) {
+__device__ void compact_scan_block(Scalars *sc, int s, long long *blk, int nblk) {
   __shared__ long long buf[BS / 64];
   const int per = (nblk + BS - 1) / BS;
   const int b0 = min((int)threadIdx.x * per, nblk), b1 = min(b0 + per, nblk);
   long long loc = 0;
-  for (int b = b0; b < b1; ++b) loc += S.blkcnt[b];
+  for (int b = b0; b < b1; ++b) loc += blk[b];
   long long tot;
   long long run = block_exclusive_scan<BS, long long>(loc, buf, tot);
   for (int b = b0; b < b1; ++b) {
-    const long long c = S.blkcnt[b];
-    S.blkcnt[b] = run;
+    const long long c = blk[b];
+    blk[b] = run;
     run += c;
   }
   if (threadIdx.x == 0) {
-    S.sc->nsort[s] = S.sc->n[s];
-    S.sc->n[s] = (unsigned long long)tot;
+    sc->nsort[s] = sc->n[s];
+    sc->n[s] = (unsigned long long)tot;
   }
 }
 
 template <int BS>
-__global__ __launch_bounds__(BS) void k_compact_write(Sim S, int s, Particles dst) {
+__device__ void compact_write_block(const Particles &P, const Particles &dst, int64_t N, const long long *blk) {
   __shared__ long long buf[BS / 64];
-  const int64_t N = (int64_t)S.sc->nsort[s];
   const int64_t chunk = push_chunk(N, gridDim.x);
   const int64_t begin = (int64_t)blockIdx.x * chunk, end = min(N, begin + chunk);
   if (begin >= end) return;
-  const Particles &P = S.p[s];
-  long long out = S.blkcnt[blockIdx.x];
+  long long out = blk[blockIdx.x];
   for (int64_t base = begin; base < end; base += (int64_t)GROUP * BS) {
     const int64_t i0 = base + (int64_t)GROUP * threadIdx.x;
     int32_t w[GROUP];
@@ -1079,10 +1100,24 @@ __global__ __launch_bounds__(BS) void k_compact_write(Sim S, int s, Particles ds
   }
 }
 
+template <int BS>
+__global__ __launch_bounds__(BS) void k_compact_count(Sim S, int s) {
+  compact_count_block<BS>(S.p[s], (int64_t)S.sc->n[s], S.blkcnt);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_compact_scan(Sim S, int s, int nblk) {
+  compact_scan_block<BS>(S.sc, s, S.blkcnt, nblk);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_compact_write(Sim S, int s, Particles dst) {
+  compact_write_block<BS>(S.p[s], dst, (int64_t)S.sc->nsort[s], S.blkcnt);
+}
+
 // ---------------------------------------------------------------- diagnostics
 template <int BS>
-__global__ __launch_bounds__(BS) void k_diag(Sim S, int s) {
-  extern __shared__ __align__(16) unsigned char dsm[];
+__device__ void diag_block(const Sim &S, int s, unsigned char *dsm) {
   const int ng = S.ng;
   unsigned long long *le = (unsigned long long *)dsm;
   unsigned int *lc = (unsigned int *)(le + ng);
@@ -1112,6 +1147,12 @@ __global__ __launch_bounds__(BS) void k_diag(Sim S, int s) {
   for (int j = threadIdx.x; j < NBIN; j += BS)
     if (lb[j]) atomicAdd(&S.edf[(size_t)s * NBIN + j], (unsigned long long)lb[j]);
   if (blockIdx.x == 0 && threadIdx.x == 0 && s == 0) S.nacc[1] += 1ull;
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_diag(Sim S, int s) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  diag_block<BS>(S, s, dsm);
 }
 
 // ---------------------------------------------------------------- loading, leapfrog start, deposit
@@ -1165,7 +1206,147 @@ __global__ __launch_bounds__(BS) void k_deposit(Sim S, int s) {
     if (dq[j]) atomicAdd(&S.Q[(size_t)s * nn + j], dq[j]);
 }
 
+// ---------------------------------------------------------------- batches
+// Many discharges advance in one launch per kernel: member m's Sim lives in
+// device memory (its particle buffers may be swapped there by the re-ordering),
+// its step is base[m] + rel, and `mask` selects the members a launch works on.
+__device__ __forceinline__ bool in_mask(uint64_t mask, int m) { return (mask >> m) & 1ull; }
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_field_b(const Sim *__restrict__ sims, const BatchDev *__restrict__ bd,
+                                                 int rel) {
+  extern __shared__ int dyn_fix[];
+  const int m = blockIdx.y;
+  if (blockIdx.x == 0) field_block<BS>(sims[m], bd->base[m] + rel, 0);
+  else fixup_block<BS>(sims[m], blockIdx.x - 1, dyn_fix);
+}
+
+// block holding tile t when Tt tiles are split into G contiguous ranges
+// [b Tt / G, (b + 1) Tt / G)
+__device__ __forceinline__ long long block_of_tile(long long t, long long Tt, long long G) {
+  return ((t + 1) * G + Tt - 1) / Tt - 1;
+}
+
+// Persistent push over all members in the mask.  The members' stores are cut
+// into tiles of one pass (GROUP * BS slots), numbered member after member; block
+// b takes the contiguous tile range b of min(grid, tiles) equal ranges, so its
+// work touches each member in at most one run.  The run's histogram goes to row
+// (b - first block of the member) of the member's partials; block 0 records the
+// number of rows per member for k_reduce_b.
+template <int BS, int S_>
+__global__ __launch_bounds__(BS, PICMCC_PUSH_WAVES) void k_push_b(const Sim *__restrict__ sims, BatchDev *bd,
+                                                                  int nmem, uint64_t mask, int rel) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ PushLds pl;
+  __shared__ long long tstart[MAXBATCH + 1];
+  __shared__ long long nslot[MAXBATCH];
+  constexpr long long TILE = (long long)GROUP * BS;
+  if (threadIdx.x < 64) {
+    const int m = threadIdx.x;
+    long long n = 0, t = 0;
+    if (m < nmem && in_mask(mask, m)) {
+      n = (long long)sims[m].sc->n[S_];
+      t = (n + TILE - 1) / TILE;
+    }
+    nslot[m] = n;
+    tstart[m + 1] = wave_incl_scan(t);
+    if (m == 0) tstart[0] = 0;
+  }
+  __syncthreads();
+  const long long Tt = tstart[nmem];
+  const long long G = min((long long)gridDim.x, Tt);
+  if (blockIdx.x == 0 && threadIdx.x < nmem) {
+    const int m = threadIdx.x;
+    int rows = 0;
+    if (tstart[m + 1] > tstart[m])
+      rows = (int)(block_of_tile(tstart[m + 1] - 1, Tt, G) - block_of_tile(tstart[m], Tt, G) + 1);
+    bd->rows[S_][m] = rows;
+  }
+  if ((long long)blockIdx.x >= G) return;
+  const long long t0 = (long long)blockIdx.x * Tt / G, t1 = ((long long)blockIdx.x + 1) * Tt / G;
+  for (int m = 0; m < nmem; ++m) {
+    const long long a = max(t0, tstart[m]), b = min(t1, tstart[m + 1]);
+    if (a >= b) continue;
+    const Sim &S = sims[m];
+    const long long row = (long long)blockIdx.x - block_of_tile(tstart[m], Tt, G);
+    const int64_t begin = (a - tstart[m]) * TILE, end = min((long long)nslot[m], (b - tstart[m]) * TILE);
+    push_run<BS, S_>(S, bd->base[m] + rel, begin, end, S.part + (size_t)row * (S.ng + 1), smem, pl);
+  }
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_reduce_b(const Sim *__restrict__ sims, const BatchDev *__restrict__ bd,
+                                                  uint64_t mask, int s) {
+  const int m = blockIdx.z;
+  if (!in_mask(mask, m)) return;
+  const Sim &S = sims[m];
+  const int nn = S.ng + 1;
+  const int j = blockIdx.x * BS + threadIdx.x;
+  if (j >= nn) return;
+  const int used = bd->rows[s][m];
+  unsigned long long sum = 0ull;
+  for (int b = blockIdx.y; b < used; b += gridDim.y) sum += S.part[(size_t)b * nn + j];
+  if (sum) atomicAdd(&S.Q[(size_t)s * nn + j], sum);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_ionprep_b(const Sim *__restrict__ sims, uint64_t mask) {
+  if (in_mask(mask, blockIdx.x)) ionprep_block<BS>(sims[blockIdx.x]);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_pair_b(const Sim *__restrict__ sims, const BatchDev *__restrict__ bd,
+                                                uint64_t mask, int rel, int r) {
+  const int m = blockIdx.y;
+  if (!in_mask(mask, m) || r > sims[m].pair_rounds) return;
+  pair_block<BS>(sims[m], bd->base[m] + rel, r);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_diag_b(const Sim *__restrict__ sims, uint64_t mask) {
+  extern __shared__ __align__(16) unsigned char dsm[];
+  const int m = blockIdx.z;
+  if (in_mask(mask, m)) diag_block<BS>(sims[m], blockIdx.y, dsm);
+}
+
+// order-preserving compaction of every species of the members in the mask; the
+// scan swaps the member's buffers, so the write goes from alt (old) to p (new)
+template <int BS>
+__global__ __launch_bounds__(BS) void k_compact_count_b(const Sim *__restrict__ sims, uint64_t mask) {
+  const int s = blockIdx.y, m = blockIdx.z;
+  if (!in_mask(mask, m)) return;
+  const Sim &S = sims[m];
+  compact_count_block<BS>(S.p[s], (int64_t)S.sc->n[s], S.blkcnt + (size_t)s * CBLK);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_compact_scan_b(Sim *sims, uint64_t mask, int nblk) {
+  const int s = blockIdx.x, m = blockIdx.y;
+  if (!in_mask(mask, m)) return;
+  Sim &S = sims[m];
+  compact_scan_block<BS>(S.sc, s, S.blkcnt + (size_t)s * CBLK, nblk);
+  if (threadIdx.x == 0) {
+    const Particles t = S.p[s];
+    S.p[s] = S.alt[s];
+    S.alt[s] = t;
+  }
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_compact_write_b(const Sim *__restrict__ sims, uint64_t mask) {
+  const int s = blockIdx.y, m = blockIdx.z;
+  if (!in_mask(mask, m)) return;
+  const Sim &S = sims[m];
+  compact_write_block<BS>(S.alt[s], S.p[s], (int64_t)S.sc->nsort[s], S.blkcnt + (size_t)s * CBLK);
+}
+
+__global__ void k_advance_b(BatchDev *bd, int nmem, int64_t add) {
+  const int m = threadIdx.x;
+  if (m < nmem) bd->base[m] += add;
+}
+
 // ---------------------------------------------------------------- launch wrappers
+size_t diag_lds_bytes(const Sim &S);
 constexpr int FBS = 1024;   // field / fixup / scan block
 constexpr int GBS = 256;    // grid-stride helper kernels
 
@@ -1264,7 +1445,7 @@ hipError_t launch_compact(const Sim &S, int s, const Particles &dst, int grid, h
 }
 
 hipError_t launch_diag(const Sim &S, int s, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_diag<GBS>), dim3(grid), dim3(GBS), (size_t)S.ng * 12 + NBIN * 4 + 16, st, S, s);
+  hipLaunchKernelGGL((k_diag<GBS>), dim3(grid), dim3(GBS), diag_lds_bytes(S), st, S, s);
   return hipGetLastError();
 }
 
@@ -1288,5 +1469,90 @@ size_t max_push_lds(const Sim &S, int block) {
   for (int s = 0; s < NSP; ++s) m = m > push_lds_bytes(S, s, block) ? m : push_lds_bytes(S, s, block);
   return m;
 }
+
+// ---------------------------------------------------------------- batch launch wrappers
+#define PUSHB_KERNEL(BS_, S__) ((const void *)k_push_b<BS_, S__>)
+static const void *push_b_fn(int block, int s) {
+  switch (block) {
+    case 256: return s == 0 ? PUSHB_KERNEL(256, 0) : s == 1 ? PUSHB_KERNEL(256, 1) : PUSHB_KERNEL(256, 2);
+    case 512: return s == 0 ? PUSHB_KERNEL(512, 0) : s == 1 ? PUSHB_KERNEL(512, 1) : PUSHB_KERNEL(512, 2);
+    case 1024: return s == 0 ? PUSHB_KERNEL(1024, 0) : s == 1 ? PUSHB_KERNEL(1024, 1) : PUSHB_KERNEL(1024, 2);
+    default: return nullptr;
+  }
+}
+#undef PUSHB_KERNEL
+
+// resident blocks per CU of the batched push (after the LDS limit is set)
+hipError_t batch_push_occupancy(int block, int s, size_t lds, int *per_cu) {
+  const void *fn = push_b_fn(block, s);
+  if (!fn) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void *)k_field_b<FBS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(2 * sizeof(int) * NBKT));
+  if (e != hipSuccess) return e;
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, block, lds);
+}
+
+hipError_t launch_field_b(const BatchLaunch &B, int rel, hipStream_t st) {
+  hipLaunchKernelGGL((k_field_b<FBS>), dim3(1 + NSP, B.nmem), dim3(FBS), 2 * sizeof(int) * NBKT, st, B.sims, B.bd,
+                     rel);
+  return hipGetLastError();
+}
+
+#define PUSHB_CASE(BS_)                                                                                       \
+  case BS_:                                                                                                   \
+    if (s == 0) hipLaunchKernelGGL((k_push_b<BS_, 0>), dim3(g), dim3(BS_), lds, st, B.sims, B.bd, B.nmem, mask, rel); \
+    else if (s == 1) hipLaunchKernelGGL((k_push_b<BS_, 1>), dim3(g), dim3(BS_), lds, st, B.sims, B.bd, B.nmem, mask, rel); \
+    else hipLaunchKernelGGL((k_push_b<BS_, 2>), dim3(g), dim3(BS_), lds, st, B.sims, B.bd, B.nmem, mask, rel); \
+    break;
+
+hipError_t launch_push_b(const BatchLaunch &B, int s, uint64_t mask, int rel, hipStream_t st) {
+  const int g = B.push_grid[s];
+  const size_t lds = B.push_lds[s];
+  switch (B.block) {
+    PUSHB_CASE(256)
+    PUSHB_CASE(512)
+    PUSHB_CASE(1024)
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+#undef PUSHB_CASE
+
+hipError_t launch_reduce_b(const BatchLaunch &B, int s, uint64_t mask, hipStream_t st) {
+  hipLaunchKernelGGL((k_reduce_b<256>), dim3((B.nn_max + 255) / 256, 16, B.nmem), dim3(256), 0, st, B.sims, B.bd,
+                     mask, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_ionprep_b(const BatchLaunch &B, uint64_t mask, hipStream_t st) {
+  hipLaunchKernelGGL((k_ionprep_b<GBS>), dim3(B.nmem), dim3(GBS), 0, st, B.sims, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_b(const BatchLaunch &B, uint64_t mask, int rel, int r, hipStream_t st) {
+  hipLaunchKernelGGL((k_pair_b<GBS>), dim3(B.pgrid, B.nmem), dim3(GBS), 0, st, B.sims, B.bd, mask, rel, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_diag_b(const BatchLaunch &B, uint64_t mask, hipStream_t st) {
+  hipLaunchKernelGGL((k_diag_b<GBS>), dim3(B.dgrid, NSP, B.nmem), dim3(GBS), B.diag_lds, st, B.sims, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_compact_b(const BatchLaunch &B, uint64_t mask, hipStream_t st) {
+  hipLaunchKernelGGL((k_compact_count_b<GBS>), dim3(B.cgrid, NSP, B.nmem), dim3(GBS), 0, st, B.sims, mask);
+  hipLaunchKernelGGL((k_compact_scan_b<FBS>), dim3(NSP, B.nmem), dim3(FBS), 0, st, B.sims, mask, B.cgrid);
+  hipLaunchKernelGGL((k_compact_write_b<GBS>), dim3(B.cgrid, NSP, B.nmem), dim3(GBS), 0, st, B.sims, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_advance_b(const BatchLaunch &B, int64_t add, hipStream_t st) {
+  hipLaunchKernelGGL(k_advance_b, dim3(1), dim3(64), 0, st, B.bd, B.nmem, add);
+  return hipGetLastError();
+}
+
+size_t diag_lds_bytes(const Sim &S) { return (size_t)S.ng * 12 + NBIN * 4 + 16; }
 
 }  // namespace picmcc

@@ -3,6 +3,7 @@
 // kernel launches of one step.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -29,6 +30,16 @@ hipError_t launch_compact(const Sim &S, int s, const Particles &dst, int grid, h
 int max_push_grid();
 size_t max_push_lds(const Sim &S, int block);
 size_t push_lds_bytes(const Sim &S, int s, int bs);
+size_t diag_lds_bytes(const Sim &S);
+hipError_t batch_push_occupancy(int block, int s, size_t lds, int *per_cu);
+hipError_t launch_field_b(const BatchLaunch &B, int rel, hipStream_t st);
+hipError_t launch_push_b(const BatchLaunch &B, int s, uint64_t mask, int rel, hipStream_t st);
+hipError_t launch_reduce_b(const BatchLaunch &B, int s, uint64_t mask, hipStream_t st);
+hipError_t launch_ionprep_b(const BatchLaunch &B, uint64_t mask, hipStream_t st);
+hipError_t launch_pair_b(const BatchLaunch &B, uint64_t mask, int rel, int r, hipStream_t st);
+hipError_t launch_diag_b(const BatchLaunch &B, uint64_t mask, hipStream_t st);
+hipError_t launch_compact_b(const BatchLaunch &B, uint64_t mask, hipStream_t st);
+hipError_t launch_advance_b(const BatchLaunch &B, int64_t add, hipStream_t st);
 }  // namespace picmcc
 
 using namespace picmcc;
@@ -166,6 +177,7 @@ struct pic_handle {
   double numax[NSP] = {0, 0, 0};
   int block = 512, grid[NSP] = {1, 1, 1}, hgrid = 1, pgrid = 1;
   int ncu = 1;
+  bool batch_busy = false;         // stepped by a batch that has not been synchronised
   std::string err;
 };
 
@@ -260,6 +272,7 @@ const char *pic_strerror(int code) {
     case PIC_ENAN: return "non-finite particle state";
     case PIC_EHIP: return "HIP runtime error";
     case PIC_ENODEVICE: return "no gfx950 device";
+    case PIC_EBUSY: return "handle busy in a batch";
     default: return "unknown error";
   }
 }
@@ -453,6 +466,7 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
 
 int pic_destroy(pic_handle *h) {
   if (!h) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   if (h->stream || true) (void)hipStreamSynchronize(h->stream);
   delete h;
   return PIC_OK;
@@ -460,6 +474,7 @@ int pic_destroy(pic_handle *h) {
 
 int pic_prepare(pic_handle *h, int32_t shift) {
   if (!h) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   Sim &S = h->S;
   const size_t nn = h->cfg.ng + 1;
   HIPCHK(h, hipMemsetAsync(S.Q, 0, 8 * NSP * nn, h->stream));
@@ -473,6 +488,7 @@ int pic_prepare(pic_handle *h, int32_t shift) {
 
 int pic_load_uniform(pic_handle *h) {
   if (!h) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   HIPCHK(h, launch_fixup(h->S, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   for (int s = 0; s < NSP; ++s) {
@@ -494,6 +510,7 @@ int pic_load_uniform(pic_handle *h) {
 int pic_set_particles(pic_handle *h, int32_t s, int64_t n, const int32_t *cell, const float *off, const float *vx,
                       const float *vy, const float *vz, const uint32_t *id, const int32_t *cd, uint32_t next_id) {
   if (!h || s < 0 || s >= NSP || n < 0) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   if (n > h->sp[s].capacity) return fail(h, PIC_ECAPACITY, "more particles than the species capacity");
   if (n > 0 && (!cell || !off || !vx || !vy || !vz || !id)) return fail(h, PIC_EINVAL, "null particle array");
   std::vector<int32_t> w((size_t)n);
@@ -539,6 +556,7 @@ int pic_sync(pic_handle *h) {
 
 int pic_count(pic_handle *h, int32_t s, int64_t *n) {
   if (!h || s < 0 || s >= NSP || !n) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   HIPCHK(h, launch_fixup(h->S, h->stream));
   hipError_t e;
   const Scalars sc = read_scalars(h, &e);
@@ -554,6 +572,7 @@ int pic_count(pic_handle *h, int32_t s, int64_t *n) {
 int pic_get_particles(pic_handle *h, int32_t s, int64_t *n, int32_t *cell, float *off, float *vx, float *vy,
                       float *vz, uint32_t *id, int32_t *cd, uint32_t *next_id) {
   if (!h || s < 0 || s >= NSP || !n) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   HIPCHK(h, launch_fixup(h->S, h->stream));
   hipError_t e;
   const Scalars sc = read_scalars(h, &e);
@@ -593,6 +612,7 @@ int pic_get_particles(pic_handle *h, int32_t s, int64_t *n, int32_t *cell, float
 
 int pic_set_step(pic_handle *h, int64_t step) {
   if (!h || step < 0) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   h->step = step;
   return PIC_OK;
 }
@@ -637,6 +657,7 @@ static int enqueue_step(pic_handle *h, hipEvent_t ev0, hipEvent_t ev1) {
 
 int pic_step(pic_handle *h, int64_t n_steps) {
   if (!h || n_steps < 0) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   for (int64_t k = 0; k < n_steps; ++k) {
     const int r = enqueue_step(h, nullptr, nullptr);
     if (r != PIC_OK) return r;
@@ -646,6 +667,7 @@ int pic_step(pic_handle *h, int64_t n_steps) {
 
 int pic_step_timed(pic_handle *h, int64_t n_steps, double *ms_push_e, double *ms_total, int64_t *launches) {
   if (!h || n_steps < 0) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   const int CH = 256;
   std::vector<hipEvent_t> ev(2 * CH);
   hipEvent_t t0, t1;
@@ -683,6 +705,7 @@ int pic_step_timed(pic_handle *h, int64_t n_steps, double *ms_push_e, double *ms
 
 int pic_moments(pic_handle *h, pic_moments_out *out, int32_t reset) {
   if (!h || !out) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   const Layout &L = h->L;
   const size_t ng = h->cfg.ng, nn = ng + 1;
   HIPCHK(h, hipStreamSynchronize(h->stream));
@@ -711,6 +734,7 @@ int pic_moments(pic_handle *h, pic_moments_out *out, int32_t reset) {
 
 int pic_get_hist(pic_handle *h, int64_t *q) {
   if (!h || !q) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   HIPCHK(h, launch_fixup(h->S, h->stream));
   HIPCHK(h, hipStreamSynchronize(h->stream));
   HIPCHK(h, hipMemcpy(q, h->S.Q, 8 * NSP * (size_t)(h->cfg.ng + 1), hipMemcpyDeviceToHost));
@@ -719,6 +743,7 @@ int pic_get_hist(pic_handle *h, int64_t *q) {
 
 int pic_get_field(pic_handle *h, double *phi, float *e) {
   if (!h) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   HIPCHK(h, hipStreamSynchronize(h->stream));
   if (phi) HIPCHK(h, hipMemcpy(phi, h->S.phi, 8 * (size_t)(h->cfg.ng + 1), hipMemcpyDeviceToHost));
   if (e) HIPCHK(h, hipMemcpy(e, h->S.E, 4 * (size_t)(h->cfg.ng + 1), hipMemcpyDeviceToHost));
@@ -727,6 +752,7 @@ int pic_get_field(pic_handle *h, double *phi, float *e) {
 
 int pic_get_counters(pic_handle *h, int64_t *out) {
   if (!h || !out) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   hipError_t e;
   const Scalars sc = read_scalars(h, &e);
   if (e != hipSuccess) return hipfail(h, e, "pic_get_counters");
@@ -736,6 +762,7 @@ int pic_get_counters(pic_handle *h, int64_t *out) {
 
 int pic_get_events(pic_handle *h, int64_t max, int64_t *rec, int64_t *n, int32_t clear) {
   if (!h || !n || max < 0) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   hipError_t e;
   const Scalars sc = read_scalars(h, &e);
   if (e != hipSuccess) return hipfail(h, e, "pic_get_events");
@@ -757,6 +784,413 @@ int pic_nu_max(pic_handle *h, int32_t s, double *nu) {
   const Scalars sc = read_scalars(h, &e);
   if (e != hipSuccess) return hipfail(h, e, "pic_nu_max");
   *nu = sc.numax_neg;
+  return PIC_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ batches
+struct pic_batch {
+  std::vector<pic_handle *> mem;
+  hipStream_t stream = nullptr;
+  unsigned char *ws = nullptr;
+  Sim *d_sims = nullptr;
+  BatchDev *d_bd = nullptr;
+  pic_batch_config cfg{};
+  int spc = 0;
+  int rel = 0;                 // steps done in the running rf cycle
+  bool on_device = false;      // the members' state lives in the device records
+  BatchLaunch B{};
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int ncu = 1;
+  size_t lds_max = 0;
+  std::vector<Sim> host_sims;
+  std::string err;
+};
+
+namespace {
+
+std::string g_batch_error;
+
+int bfail(pic_batch *b, int code, const std::string &m) {
+  if (b) b->err = m;
+  else g_batch_error = m;
+  return code;
+}
+
+#define BHIP(b, expr)                                                                               \
+  do {                                                                                              \
+    hipError_t e_ = (expr);                                                                         \
+    if (e_ != hipSuccess) return bfail((b), PIC_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+size_t batch_bytes(int n) {
+  return ((sizeof(Sim) * (size_t)n + 255) & ~(size_t)255) + ((sizeof(BatchDev) + 255) & ~(size_t)255);
+}
+
+uint64_t all_mask(int n) { return n >= 64 ? ~0ull : ((1ull << n) - 1ull); }
+
+int batch_check_config(const pic_batch_config *c, int spc, std::string &msg) {
+  if (!c) { msg = "null batch config"; return PIC_EINVAL; }
+  if (!(c->block == 0 || c->block == 256 || c->block == 512 || c->block == 1024)) {
+    msg = "batch block must be 0, 256, 512 or 1024"; return PIC_EINVAL;
+  }
+  if (c->sort_every < 0 || (c->sort_every > 0 && spc % c->sort_every != 0)) {
+    msg = "batch sort_every must be 0 or divide steps_per_cycle"; return PIC_EINVAL;
+  }
+  if (c->grid < 0 || c->grid > max_push_grid()) { msg = "batch grid must be in [0, 2048]"; return PIC_EINVAL; }
+  return PIC_OK;
+}
+
+void drop_graph(pic_batch *b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+// launch shapes for the current configuration
+int batch_shapes(pic_batch *b) {
+  BatchLaunch &B = b->B;
+  B.sims = b->d_sims;
+  B.bd = b->d_bd;
+  B.nmem = (int)b->mem.size();
+  B.block = b->cfg.block ? b->cfg.block : 512;
+  B.nn_max = 0;
+  B.diag_lds = 0;
+  for (pic_handle *h : b->mem) {
+    B.nn_max = std::max(B.nn_max, h->cfg.ng + 1);
+    B.diag_lds = std::max(B.diag_lds, diag_lds_bytes(h->S));
+  }
+  for (int s = 0; s < NSP; ++s) {
+    size_t lds = 0;
+    for (pic_handle *h : b->mem) lds = std::max(lds, push_lds_bytes(h->S, s, B.block));
+    if (lds > b->lds_max) return bfail(b, PIC_EINVAL, "largest member grid does not fit the LDS of one block");
+    int per_cu = 0;
+    BHIP(b, batch_push_occupancy(B.block, s, lds, &per_cu));
+    const int g = b->cfg.grid ? b->cfg.grid : std::max(1, per_cu) * b->ncu;
+    B.push_grid[s] = std::min(g, max_push_grid());
+    B.push_lds[s] = lds;
+  }
+  B.cgrid = 64;
+  B.pgrid = 16;
+  B.dgrid = 32;
+  return PIC_OK;
+}
+
+// the members' records go to the device; from here the batch owns their state
+int batch_upload(pic_batch *b) {
+  const int n = (int)b->mem.size();
+  b->host_sims.resize(n);
+  BatchDev bd;
+  std::memset(&bd, 0, sizeof(bd));
+  for (int m = 0; m < n; ++m) {
+    pic_handle *h = b->mem[m];
+    if (h->step % b->spc != 0)
+      return bfail(b, PIC_EINVAL, "member " + std::to_string(m) + " is not at an rf-cycle boundary");
+    Sim S = h->S;
+    for (int s = 0; s < NSP; ++s) {
+      S.p[s] = h->buf[s][h->cur[s]];
+      S.alt[s] = h->buf[s][1 - h->cur[s]];
+    }
+    b->host_sims[m] = S;
+    bd.base[m] = h->step;
+  }
+  BHIP(b, hipMemcpyAsync(b->d_sims, b->host_sims.data(), sizeof(Sim) * n, hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipMemcpyAsync(b->d_bd, &bd, sizeof(bd), hipMemcpyHostToDevice, b->stream));
+  BHIP(b, hipStreamSynchronize(b->stream));
+  for (pic_handle *h : b->mem) h->batch_busy = true;
+  b->on_device = true;
+  b->rel = 0;
+  return PIC_OK;
+}
+
+// the launches of step `r` of the rf cycle (device steps base[m] + r)
+int launch_batch_step(pic_batch *b, int r) {
+  const BatchLaunch &B = b->B;
+  hipStream_t st = b->stream;
+  const int n = B.nmem;
+  const uint64_t all = all_mask(n);
+  uint64_t dmask = 0ull, imask = 0ull;
+  int R = 0;
+  for (int m = 0; m < n; ++m) {
+    const pic_config &c = b->mem[m]->cfg;
+    if (c.diag_every > 0 && r % c.diag_every == 0) dmask |= 1ull << m;
+    if (r % c.ksub == 0) {
+      imask |= 1ull << m;
+      R = std::max(R, c.pair_rounds);
+    }
+  }
+  BHIP(b, launch_field_b(B, r, st));
+  if (dmask) BHIP(b, launch_diag_b(B, dmask, st));
+  if (b->cfg.sort_every > 0 && r % b->cfg.sort_every == 0) BHIP(b, launch_compact_b(B, all, st));
+  BHIP(b, launch_push_b(B, 0, all, r, st));
+  BHIP(b, launch_reduce_b(B, 0, all, st));
+  if (imask) {
+    BHIP(b, launch_push_b(B, 1, imask, r, st));
+    BHIP(b, launch_reduce_b(B, 1, imask, st));
+    BHIP(b, launch_ionprep_b(B, imask, st));
+    BHIP(b, launch_push_b(B, 2, imask, r, st));
+    BHIP(b, launch_reduce_b(B, 2, imask, st));
+    for (int k = 0; k <= R; ++k) BHIP(b, launch_pair_b(B, imask, r, k, st));
+  }
+  if (r == b->spc - 1) BHIP(b, launch_advance_b(B, b->spc, st));
+  return PIC_OK;
+}
+
+void batch_advance_host(pic_batch *b, int64_t steps) {
+  for (pic_handle *h : b->mem) h->step += steps;
+  b->rel = (int)((b->rel + steps) % b->spc);
+}
+
+int batch_capture(pic_batch *b) {
+  BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  int rc = PIC_OK;
+  for (int r = 0; r < b->spc && rc == PIC_OK; ++r) rc = launch_batch_step(b, r);
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->stream, &g);
+  if (rc != PIC_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  if (e != hipSuccess) return bfail(b, PIC_EHIP, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+  b->graph = g;
+  BHIP(b, hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return PIC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_batch_query(int32_t n_members, uint64_t *workspace_bytes) {
+  if (n_members < 1 || n_members > MAXBATCH || !workspace_bytes) {
+    g_batch_error = "n_members must be in [1, 64] and workspace_bytes non-null";
+    return PIC_EINVAL;
+  }
+  *workspace_bytes = batch_bytes(n_members);
+  return PIC_OK;
+}
+
+int pic_batch_create(pic_handle *const *members, int32_t n, const pic_batch_config *cfg, void *workspace,
+                     uint64_t workspace_bytes, void *stream, pic_batch **out) {
+  if (!members || !out || !workspace || n < 1 || n > MAXBATCH)
+    return bfail(nullptr, PIC_EINVAL, "need 1..64 members, a workspace and an output pointer");
+  if (workspace_bytes < batch_bytes(n)) return bfail(nullptr, PIC_EINVAL, "workspace smaller than pic_batch_query reported");
+  const int spc = members[0] ? members[0]->cfg.steps_per_cycle : 0;
+  std::string msg;
+  if (batch_check_config(cfg, spc, msg) != PIC_OK) return bfail(nullptr, PIC_EINVAL, msg);
+  for (int m = 0; m < n; ++m) {
+    const pic_handle *h = members[m];
+    const std::string who = "member " + std::to_string(m) + ": ";
+    if (!h) return bfail(nullptr, PIC_EINVAL, who + "null handle");
+    for (int k = 0; k < m; ++k)
+      if (members[k] == h) return bfail(nullptr, PIC_EINVAL, who + "listed twice");
+    if (h->batch_busy) return bfail(nullptr, PIC_EBUSY, who + "busy in another batch");
+    if (h->stream != (hipStream_t)stream) return bfail(nullptr, PIC_EINVAL, who + "created on another stream");
+    const pic_config &c = h->cfg;
+    if (c.steps_per_cycle != spc) return bfail(nullptr, PIC_EINVAL, who + "steps_per_cycle differs");
+    if (spc % c.ksub != 0) return bfail(nullptr, PIC_EINVAL, who + "ksub must divide steps_per_cycle");
+    if (c.diag_every > 0 && spc % c.diag_every != 0)
+      return bfail(nullptr, PIC_EINVAL, who + "diag_every must divide steps_per_cycle");
+    if (c.grid != 0) return bfail(nullptr, PIC_EINVAL, who + "grid must be 0 (full partial storage)");
+  }
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return bfail(nullptr, PIC_ENODEVICE, "no HIP device");
+  pic_batch *b = new pic_batch();
+  b->mem.assign(members, members + n);
+  b->stream = (hipStream_t)stream;
+  b->ws = (unsigned char *)workspace;
+  b->d_sims = (Sim *)b->ws;
+  b->d_bd = (BatchDev *)(b->ws + ((sizeof(Sim) * (size_t)n + 255) & ~(size_t)255));
+  b->cfg = *cfg;
+  b->spc = spc;
+  b->ncu = prop.multiProcessorCount;
+  b->lds_max = prop.sharedMemPerBlock;
+  const int rc = batch_shapes(b);
+  if (rc != PIC_OK) {
+    g_batch_error = b->err;
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return PIC_OK;
+}
+
+int pic_batch_step_cycles(pic_batch *b, int64_t cycles) {
+  if (!b || cycles < 0) return bfail(b, PIC_EINVAL, "null batch or negative cycle count");
+  if (cycles == 0) return PIC_OK;
+  if (!b->on_device) {
+    const int rc = batch_upload(b);
+    if (rc != PIC_OK) return rc;
+  }
+  if (b->rel != 0) return bfail(b, PIC_EINVAL, "batch not at an rf-cycle boundary");
+  if (b->cfg.use_graph && b->stream) {
+    if (!b->exec) {
+      const int rc = batch_capture(b);
+      if (rc != PIC_OK) return rc;
+    }
+    for (int64_t c = 0; c < cycles; ++c) {
+      BHIP(b, hipGraphLaunch(b->exec, b->stream));
+      batch_advance_host(b, b->spc);
+    }
+    return PIC_OK;
+  }
+  for (int64_t c = 0; c < cycles; ++c)
+    for (int r = 0; r < b->spc; ++r) {
+      const int rc = launch_batch_step(b, r);
+      if (rc != PIC_OK) return rc;
+      batch_advance_host(b, 1);
+    }
+  return PIC_OK;
+}
+
+int pic_batch_sync(pic_batch *b) {
+  if (!b) return bfail(b, PIC_EINVAL, "null batch");
+  BHIP(b, hipStreamSynchronize(b->stream));
+  const int n = (int)b->mem.size();
+  if (b->on_device) {
+    BHIP(b, hipMemcpy(b->host_sims.data(), b->d_sims, sizeof(Sim) * n, hipMemcpyDeviceToHost));
+    for (int m = 0; m < n; ++m) {
+      pic_handle *h = b->mem[m];
+      for (int s = 0; s < NSP; ++s) {
+        h->cur[s] = b->host_sims[m].p[s].w == h->buf[s][0].w ? 0 : 1;
+        h->S.p[s] = h->buf[s][h->cur[s]];
+      }
+      h->batch_busy = false;
+    }
+    b->on_device = false;
+  }
+  for (int m = 0; m < n; ++m) {
+    const int rc = pic_sync(b->mem[m]);
+    if (rc != PIC_OK) return bfail(b, rc, "member " + std::to_string(m) + ": " + b->mem[m]->err);
+  }
+  return PIC_OK;
+}
+
+int pic_batch_set_config(pic_batch *b, const pic_batch_config *cfg) {
+  if (!b) return bfail(b, PIC_EINVAL, "null batch");
+  std::string msg;
+  if (batch_check_config(cfg, b->spc, msg) != PIC_OK) return bfail(b, PIC_EINVAL, msg);
+  const pic_batch_config old = b->cfg;
+  b->cfg = *cfg;
+  drop_graph(b);
+  const int rc = batch_shapes(b);
+  if (rc != PIC_OK) {
+    b->cfg = old;
+    (void)batch_shapes(b);
+  }
+  return rc;
+}
+
+int pic_batch_get_config(const pic_batch *b, pic_batch_config *cfg) {
+  if (!b || !cfg) return PIC_EINVAL;
+  *cfg = b->cfg;
+  if (!cfg->block) cfg->block = b->B.block;
+  return PIC_OK;
+}
+
+int pic_batch_autotune(pic_batch *b, int32_t window, pic_batch_tuning *out) {
+  if (!b || !out) return bfail(b, PIC_EINVAL, "null batch or output");
+  if (window < 1 || b->spc % window != 0) return bfail(b, PIC_EINVAL, "window must divide steps_per_cycle");
+  if (!b->on_device) {
+    const int rc = batch_upload(b);
+    if (rc != PIC_OK) return rc;
+  }
+  if (b->rel != 0) return bfail(b, PIC_EINVAL, "batch not at an rf-cycle boundary");
+  const pic_batch_config keep = b->cfg;
+  const int blocks[3] = {256, 512, 1024};
+  const int sorts[7] = {10, 20, 50, 100, 200, 500, 1000};
+  std::memset(out, 0, sizeof(*out));
+  hipEvent_t e0, e1;
+  BHIP(b, hipEventCreate(&e0));
+  BHIP(b, hipEventCreate(&e1));
+  int rc = PIC_OK;
+  double best = 1e300;
+  for (int bi = 0; bi < 3 && rc == PIC_OK; ++bi)
+    for (int si = 0; si < 7 && rc == PIC_OK; ++si) {
+      const int S = sorts[si];
+      if (window % S != 0 || b->spc % S != 0 || out->n >= PIC_TUNE_MAX) continue;
+      pic_batch_config c = keep;
+      c.block = blocks[bi];
+      c.sort_every = S;
+      c.use_graph = 0;
+      if (pic_batch_set_config(b, &c) != PIC_OK) { rc = PIC_OK; b->err.clear(); continue; }   // does not fit
+      if (hipEventRecord(e0, b->stream) != hipSuccess) { rc = bfail(b, PIC_EHIP, "hipEventRecord"); break; }
+      for (int k = 0; k < window && rc == PIC_OK; ++k) {
+        rc = launch_batch_step(b, b->rel);
+        if (rc == PIC_OK) batch_advance_host(b, 1);
+      }
+      if (rc != PIC_OK) break;
+      float ms = 0.0f;
+      if (hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+        rc = bfail(b, PIC_EHIP, "trial timing");
+        break;
+      }
+      const int k = out->n++;
+      out->block[k] = c.block;
+      out->sort_every[k] = S;
+      out->ms_per_step[k] = (double)ms / window;
+      if (out->ms_per_step[k] < best) { best = out->ms_per_step[k]; out->best = k; }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != PIC_OK) return rc;
+  if (out->n == 0) return bfail(b, PIC_EINVAL, "no candidate fits (window must be a multiple of 10)");
+  pic_batch_config c = keep;
+  c.block = out->block[out->best];
+  c.sort_every = out->sort_every[out->best];
+  rc = pic_batch_set_config(b, &c);
+  if (rc != PIC_OK) return rc;
+  while (b->rel != 0) {                       // finish the rf cycle with the chosen launch shapes
+    rc = launch_batch_step(b, b->rel);
+    if (rc != PIC_OK) return rc;
+    batch_advance_host(b, 1);
+  }
+  BHIP(b, hipStreamSynchronize(b->stream));
+  return PIC_OK;
+}
+
+int pic_batch_destroy(pic_batch *b) {
+  if (!b) return PIC_EINVAL;
+  (void)hipStreamSynchronize(b->stream);
+  if (b->on_device) (void)pic_batch_sync(b);
+  drop_graph(b);
+  for (pic_handle *h : b->mem) h->batch_busy = false;
+  delete b;
+  return PIC_OK;
+}
+
+const char *pic_batch_last_error(const pic_batch *b) { return b ? b->err.c_str() : g_batch_error.c_str(); }
+
+int pic_ksub_select(const pic_config *c, const pic_species *sp, double n_ion_max, double phi_max, int32_t *ksub) {
+  if (!c || !sp || !ksub) { g_query_error = "null argument"; return PIC_EINVAL; }
+  if (!finite_pos(c->L) || c->ng < 2 || !finite_pos(c->f) || c->steps_per_cycle < 1 ||
+      !(std::isfinite(n_ion_max) && n_ion_max >= 0.0) || !(std::isfinite(phi_max) && phi_max >= 0.0)) {
+    g_query_error = "need L > 0, ng >= 2, f > 0, steps_per_cycle >= 1, n_ion_max >= 0, phi_max >= 0";
+    return PIC_EINVAL;
+  }
+  for (int s = 1; s < NSP; ++s)
+    if (!finite_pos(sp[s].mass)) { g_query_error = "ion masses must be > 0"; return PIC_EINVAL; }
+  const double dt = 1.0 / (c->f * c->steps_per_cycle), dx = c->L / c->ng;
+  int best = 1;
+  for (int k = 1; k <= c->steps_per_cycle; ++k) {
+    if (c->steps_per_cycle % k != 0) continue;
+    bool ok = true;
+    for (int s = 1; s < NSP; ++s) {
+      const double M = sp[s].mass;
+      const double wpi = std::sqrt(n_ion_max * QE * QE / (EPS0 * M));
+      const double vmax = std::sqrt(2.0 * QE * phi_max / M);
+      if (wpi * k * dt > 0.2 || vmax * k * dt > dx) ok = false;
+    }
+    if (!ok) break;                  // both limits grow with k
+    best = k;
+  }
+  *ksub = best;
   return PIC_OK;
 }
 

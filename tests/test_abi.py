@@ -79,3 +79,50 @@ def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(B, "LIB_PATH", "/nonexistent/libpicmcc.so")
     with pytest.raises(RuntimeError):
         B.lib()
+
+
+def test_batch_query_sizes_and_limits():
+    assert B.pic_batch_query(1) > 0
+    assert B.pic_batch_query(64) > B.pic_batch_query(1)
+    for n in (0, 65):
+        with pytest.raises(B.PicError):
+            B.pic_batch_query(n)
+
+
+def _ksub_expected(d, species, n_ion, phi):
+    """Largest divisor k of the steps per cycle with omega_pi k dt <= 0.2 and
+    sqrt(2 e phi / M) k dt <= dx for both ion species (host rule, restated)."""
+    eps0, qe = 8.8541878128e-12, 1.602176634e-19
+    dt, dx = 1.0 / (d.f * d.steps_per_cycle), d.L / d.ng
+    best = 1
+    for k in range(1, d.steps_per_cycle + 1):
+        if d.steps_per_cycle % k:
+            continue
+        ok = all(np.sqrt(n_ion * qe * qe / (eps0 * s.mass)) * k * dt <= 0.2 and
+                 np.sqrt(2 * qe * phi / s.mass) * k * dt <= dx for s in species[1:])
+        if not ok:
+            break
+        best = k
+    return best
+
+
+def test_ksub_select_physics_valid_subcycling():
+    d = I.config(2)
+    sp = B.make_species(d.species())
+    cfg = B.make_config(d)
+    # nothing limits: every divisor is valid, the cycle itself is returned
+    assert B.pic_ksub_select(cfg, sp, 0.0, 0.0) == d.steps_per_cycle
+    ks = []
+    for U in (50.0, 100.0, 200.0, 400.0, 600.0):
+        k = B.pic_ksub_select(cfg, sp, 3e15, U)
+        assert d.steps_per_cycle % k == 0
+        assert k == _ksub_expected(d, d.species(), 3e15, U)
+        ks.append(k)
+    assert ks == sorted(ks, reverse=True) and ks[0] > ks[-1]      # harder drive, shorter ion steps
+    # a finer grid never allows a longer ion step
+    fine = B.make_config(I.config(2, ng=2048))
+    assert B.pic_ksub_select(fine, sp, 3e15, 400.0) <= B.pic_ksub_select(cfg, sp, 3e15, 400.0)
+    # plasma-frequency limit alone: omega_pi k dt <= 0.2 at a huge density forces k = 1
+    assert B.pic_ksub_select(cfg, sp, 1e22, 0.0) == 1
+    with pytest.raises(B.PicError):
+        B.pic_ksub_select(cfg, sp, -1.0, 100.0)

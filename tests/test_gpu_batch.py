@@ -1,0 +1,164 @@
+"""Batched discharges: one launch per kernel per step over many members, one
+HIP graph per rf cycle, and the autotuner.  A member advanced in a batch must
+reach exactly the state of the same discharge advanced alone (same random
+streams; launch shapes and re-ordering change the storage order only), so
+everything is compared bit for bit, matched by particle id."""
+import numpy as np
+import pytest
+
+from paper_0705_0497_amd import inputs as I
+from tests import helpers as H
+
+pytestmark = pytest.mark.gpu
+
+SPC = 40
+
+
+def _members(spec, **over):
+    """Small sweep members: (index, ksub, superparticles) with 40 steps per cycle."""
+    return [I.sweep_member(j, steps_per_cycle=SPC, ksub=k, n_total=n, diag_every=10, sort_every=20, **over)
+            for j, k, n in spec]
+
+
+def _snapshot(g):
+    parts = [H.by_id(g.get_particles(s)[0]) for s in range(3)]
+    m = g.moments()
+    return {"parts": parts, "hist": g.hist(), "counters": g.counters(), "moments": m, "step": g.step_index}
+
+
+def _same(a, b, who):
+    assert a["step"] == b["step"], who
+    for s in range(3):
+        assert len(a["parts"][s]["id"]) == len(b["parts"][s]["id"]), (who, s)
+        for k in ("cell", "off", "vx", "vy", "vz", "id", "cd"):
+            np.testing.assert_array_equal(a["parts"][s][k], b["parts"][s][k], err_msg=f"{who} species {s} {k}")
+    np.testing.assert_array_equal(a["hist"], b["hist"], err_msg=who)
+    np.testing.assert_array_equal(a["counters"], b["counters"], err_msg=who)
+    for k in ("sum_q", "sum_phi", "esum", "ecnt", "edf", "iedf", "nacc", "ndiag"):
+        np.testing.assert_array_equal(a["moments"][k], b["moments"][k], err_msg=f"{who} {k}")
+
+
+def _alone(ds, procs, stream, steps):
+    from paper_0705_0497_amd.binding import Discharge
+    out = []
+    for d in ds:
+        g = Discharge(d, procs, stream=stream)
+        g.load_uniform()
+        g.step(steps)
+        out.append(_snapshot(g))
+        g.close()
+    return out
+
+
+def _loaded(ds, procs, stream):
+    from paper_0705_0497_amd.binding import Discharge
+    mem = [Discharge(d, procs, stream=stream) for d in ds]
+    for g in mem:
+        g.load_uniform()
+    return mem
+
+
+SPEC = [(0, 2, 6000), (1, 4, 15000), (2, 5, 3000), (3, 8, 9000), (4, 10, 4000)]
+
+
+def test_batch_member_equals_discharge_alone_graph_replays():
+    import torch
+    from paper_0705_0497_amd.binding import Batch
+    stream = torch.cuda.Stream()
+    ds = _members(SPEC)
+    procs = H.neutralising(I.make_processes())
+    ref1 = _alone(ds, procs, stream, SPC)
+    ref3 = _alone(ds, procs, stream, 3 * SPC)
+    mem = _loaded(ds, procs, stream)
+    b = Batch(mem, block=256, sort_every=10, use_graph=True)
+    print("batch: 5 members, graph, cycle 1", flush=True)
+    b.step_cycles(1)
+    b.sync()
+    for m, g in enumerate(mem):
+        _same(_snapshot(g), ref1[m], f"member {m} after 1 cycle")
+    print("batch: cycles 2-3 (two more replays after eager work)", flush=True)
+    b.step_cycles(2)
+    b.sync()
+    for m, g in enumerate(mem):
+        _same(_snapshot(g), ref3[m], f"member {m} after 3 cycles")
+    b.close()
+
+
+def test_batch_direct_launches_and_launch_shapes():
+    import torch
+    from paper_0705_0497_amd.binding import Batch
+    stream = torch.cuda.Stream()
+    ds = _members(SPEC[:3])
+    procs = H.neutralising(I.make_processes())
+    ref = _alone(ds, procs, stream, 2 * SPC)
+    for kw in ({"block": 1024, "sort_every": 0, "use_graph": False},
+               {"block": 512, "sort_every": 20, "use_graph": False, "grid": 3},
+               {"block": 256, "sort_every": 40, "use_graph": True, "grid": 1}):
+        print("batch shapes", kw, flush=True)
+        mem = _loaded(ds, procs, stream)
+        b = Batch(mem, **kw)
+        b.step_cycles(2)
+        b.sync()
+        for m, g in enumerate(mem):
+            _same(_snapshot(g), ref[m], f"member {m} {kw}")
+        b.close()
+        for g in mem:
+            g.close()
+
+
+def test_autotuner_picks_a_candidate_and_keeps_results():
+    import torch
+    from paper_0705_0497_amd.binding import Batch
+    stream = torch.cuda.Stream()
+    ds = _members(SPEC[:2])
+    procs = I.make_processes()
+    mem = _loaded(ds, procs, stream)
+    b = Batch(mem, block=512, sort_every=20, use_graph=True)
+    print("autotune window 20", flush=True)
+    t = b.autotune(window=20)
+    b.step_cycles(1)
+    b.sync()
+    trials = t["trials"]
+    assert len(trials) == 6                                  # 3 blocks x sort_every in {10, 20}
+    assert {(x["block"], x["sort_every"]) for x in trials} == {(bs, s) for bs in (256, 512, 1024) for s in (10, 20)}
+    assert all(x["ms_per_step"] > 0 for x in trials)
+    best = min(trials, key=lambda x: x["ms_per_step"])
+    cfg = b.config()
+    assert (cfg["block"], cfg["sort_every"]) == (best["block"], best["sort_every"])
+    steps = mem[0].step_index
+    assert steps % SPC == 0 and steps == 6 * 20 + SPC
+    ref = _alone(ds, procs, stream, steps)
+    for m, g in enumerate(mem):
+        _same(_snapshot(g), ref[m], f"member {m} after autotune")
+    b.close()
+
+
+def test_batch_validation_and_busy_members():
+    import torch
+    from paper_0705_0497_amd import binding as B
+    stream = torch.cuda.Stream()
+    procs = I.make_processes()
+    ds = _members(SPEC[:2])
+    mem = _loaded(ds, procs, stream)
+    other = B.Discharge(ds[0], procs, stream=torch.cuda.Stream())
+    with pytest.raises(B.PicError) as e:
+        B.Batch([mem[0], other])
+    assert e.value.code == B.PIC_EINVAL                      # members on different streams
+    bad = B.Discharge(_members([(5, 3, 2000)])[0], procs, stream=stream)   # ksub 3 does not divide 40
+    with pytest.raises(B.PicError):
+        B.Batch([mem[0], bad])
+    with pytest.raises(B.PicError):
+        B.Batch([mem[0], mem[0]])
+    with pytest.raises(B.PicError):
+        B.Batch(mem, sort_every=7)                           # does not divide the cycle
+    b = B.Batch(mem, sort_every=20)
+    b.step_cycles(1)
+    with pytest.raises(B.PicError) as e:
+        mem[0].get_particles(0)
+    assert e.value.code == B.PIC_EBUSY
+    b.sync()
+    assert mem[0].step_index == SPC
+    mem[0].step(1)                                           # off the cycle boundary
+    with pytest.raises(B.PicError):
+        b.step_cycles(1)
+    b.close()
