@@ -9,7 +9,7 @@ GPU before the timed region starts.
 Prints one JSON line.  Roofline of the dominant kernel (electron
 push+MCC+deposit): algorithmic bytes per launch / mean launch duration from
 HIP events on the handle's stream.  cpu_baseline: the FP64 oracle on a bounded
-sample of the same workload (1/8 of the particles, 40 steps) on the host.
+sample of the same workload (1/4 of the particles, 120 steps) on the host.
 """
 import argparse
 import hashlib
@@ -53,22 +53,22 @@ def measured_traffic(particles_per_launch):
 
 
 def cpu_baseline(d, procs):
-    """FP64 oracle on 1/8 of the particles of the same discharge, 40 steps."""
+    """FP64 oracle on 1/4 of the particles of the same discharge, 120 steps."""
     import dataclasses
     from oracle import pyoracle as po
-    counts = tuple(c // 8 for c in d.species_counts())
+    counts = tuple(c // 4 for c in d.species_counts())
     ds = dataclasses.replace(d, counts=counts)
     o = po.Oracle(ds, ds.species(), procs)
     o.load_uniform()
     o.prepare(True)
     c0 = o.counters()
-    steps = 40
+    steps = 120
     t0 = time.perf_counter()
     o.step(steps)
     dt = time.perf_counter() - t0
     pushes = int((o.counters() - c0)[0:3].sum())
     return {"value": pushes / dt, "unit": "particle-steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"same discharge with 1/8 of the superparticles ({sum(counts)}), {steps} steps "
+            "sample": f"same discharge with 1/4 of the superparticles ({sum(counts)}), {steps} steps "
                       f"incl. {steps // d.ksub} ion steps, single thread, {pushes} pushes in {dt:.1f} s"}
 
 
@@ -83,6 +83,10 @@ def main():
     ap.add_argument("--sort", choices=("compact", "cell"), default="compact",
                     help="periodic re-ordering: order-preserving compaction or counting sort by cell")
     ap.add_argument("--sort-every", type=int, default=2000)
+    ap.add_argument("--workload", choices=("single", "sweep"), default="single",
+                    help="single: the 4096-cell discharge; sweep: 64 discharges advanced as one batch")
+    ap.add_argument("--members", type=int, default=64, help="sweep: discharges in the batch")
+    ap.add_argument("--tune-window", type=int, default=200, help="sweep: autotuner trial length [steps]")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs one discharge on one GPU; --gpus {args.gpus} is not supported "
@@ -95,6 +99,8 @@ def main():
     from paper_0705_0497_amd.binding import Discharge, C_PUSH, C_CAND, C_REDRAW, C_EVENT
 
     torch.cuda.set_device(0)
+    if args.workload == "sweep":
+        return sweep(args)
     d = I.config(3)
     procs = I.make_processes()
     log(f"bench: loading {d.name} ({sum(d.species_counts())} superparticles, {d.ng} cells)")
@@ -162,6 +168,89 @@ def main():
         log("bench: timing the FP64 oracle on the host (bounded sample)")
         out["cpu_baseline"] = cpu_baseline(d, procs)
     print(json.dumps(out), flush=True)
+
+
+def sweep(args):
+    """64 discharges (U ~ U[100, 600] V, p ~ logU[5, 100] Pa, 256..1024 cells,
+    5e4..2e6 superparticles per species) advanced as one batch: one launch per
+    kernel per step, one HIP graph per rf cycle; ion subcycling per member from
+    the physics-valid rule, block size and re-ordering interval from the
+    autotuner.  One bench step = one rf cycle of the whole batch."""
+    import torch
+    from paper_0705_0497_amd import inputs as I
+    from paper_0705_0497_amd import binding as B
+
+    procs = I.make_processes()
+    stream = torch.cuda.Stream()
+    members, ksubs = [], []
+    for j in range(args.members):
+        d = I.sweep_member(j, diag_every=100)
+        k = B.pic_ksub_select(B.make_config(d), B.make_species(d.species()), 3.0 * d.n_plus0, d.U)
+        d = I.sweep_member(j, diag_every=100, ksub=k)
+        g = B.Discharge(d, procs, stream=stream)
+        g.load_uniform()
+        members.append(g)
+        ksubs.append(k)
+    loaded = sum(sum(g.d.species_counts()) for g in members)
+    log(f"bench: sweep of {len(members)} discharges, {loaded} superparticles, ksub {sorted(set(ksubs))}")
+    b = B.Batch(members, block=512, sort_every=100, use_graph=True)
+    t0 = time.perf_counter()
+    tune = b.autotune(window=args.tune_window)
+    b.sync()
+    log(f"bench: autotune {time.perf_counter() - t0:.1f} s -> {tune['best']}")
+    spc = members[0].d.steps_per_cycle
+    for c in range(args.warmup):
+        b.step_cycles(1)
+        b.sync()
+        log(f"bench: warmup cycle {c + 1}/{args.warmup} done")
+    c0 = [g.counters() for g in members]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for c in range(args.steps):
+        b.step_cycles(1)
+        if (c + 1) % 5 == 0 or c + 1 == args.steps:
+            b.sync()
+            log(f"bench: timed cycle {c + 1}/{args.steps}")
+    b.sync()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    dc = [g.counters() - a for g, a in zip(members, c0)]
+    end_counts = [sum(g.count(s) for s in range(3)) for g in members]
+    pushes = sum(int(x[B.C_PUSH:B.C_PUSH + 3].sum()) for x in dc)
+    push_e = sum(int(x[B.C_PUSH]) for x in dc)
+    cand = sum(int(x[B.C_CAND] + x[B.C_REDRAW]) for x in dc)
+    kinds = [p.kind for p in procs]
+    born = sum(2 * sum(int(x[B.C_EVENT + i]) for i, k in enumerate(kinds) if k == "ionize") +
+               sum(int(x[B.C_EVENT + i]) for i, k in enumerate(kinds) if k == "attach") for x in dc)
+    alg = BYTES_PUSH * push_e + BYTES_CAND * cand + BYTES_PRODUCT * born
+    achieved = alg / elapsed / 1e9
+    cfg = b.config()
+    out = {
+        "metric": "particle-steps/s (push+deposit+MCC); rf cycles to steady state, warm vs cold",
+        "value": pushes / elapsed,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"batched sweep of {len(members)} O2 CCP discharges (L=2.5 cm, U 100-600 V, "
+                               "p 5-100 Pa, 256-1024 cells, 5e4-2e6 superparticles per species)",
+                   "step": "one rf cycle of every member = 2000 electron steps", "cells": [g.ng for g in members],
+                   "ksub": ksubs, "superparticles_loaded": loaded, "superparticles_end": sum(end_counts),
+                   "electron_pushes": push_e,
+                   "ion_pushes": pushes - push_e, "autotuned": cfg, "autotune_trials": tune["trials"],
+                   "graph": "one HIP graph per rf cycle", "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "whole batched step (algorithmic push bytes over wall time)"},
+    }
+    print(json.dumps(out), flush=True)
+    b.close()
 
 
 if __name__ == "__main__":

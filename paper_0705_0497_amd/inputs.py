@@ -252,4 +252,10 @@ def sweep_member(j: int, seed: int = 4000, **over) -> Discharge:
     d = Discharge(f"sweep{j}", L=0.025, ng=ng, U=U, f=13.56e6, p=p, steps_per_cycle=2000,
                   ksub=20, cycles=1, n_plus0=1e15, frac_minus=0.5, n_total=int(3 * nps),
                   seed=seed + j)
-    return dataclasses.replace(d, **over)
+    d = dataclasses.replace(d, **over)
+    if "capacities" not in over:
+        # electrons and O2+ multiply several-fold on the way from the uniform load
+        # to the driven steady state; O- are lost to neutralisation and detachment
+        c = d.species_counts()
+        d = dataclasses.replace(d, capacities=(12 * c[0] + 4096, 12 * c[1] + 4096, 4 * c[2] + 4096))
+    return d
