@@ -32,6 +32,9 @@ EXPORTS = ("pic_version", "pic_query", "pic_create", "pic_destroy", "pic_load_un
            "pic_batch_query", "pic_batch_create", "pic_batch_step_cycles", "pic_batch_sync",
            "pic_batch_set_config", "pic_batch_get_config", "pic_batch_autotune", "pic_batch_destroy",
            "pic_batch_last_error", "pic_ksub_select")
+MLP_EXPORTS = ("mlp_query", "mlp_create", "mlp_destroy", "mlp_set_params", "mlp_get_params", "mlp_forward",
+               "mlp_backward", "mlp_get_grads", "mlp_adam", "mlp_last_error")
+MLP_NPARAM = 199942
 
 
 class PicError(RuntimeError):
@@ -122,6 +125,17 @@ def lib():
         L.pic_batch_last_error.restype = C.c_char_p
         L.pic_batch_last_error.argtypes = [vp]
         L.pic_ksub_select.argtypes = [P(pic_config), P(pic_species), dbl, dbl, P(i32)]
+        L.mlp_query.argtypes = [i32, P(C.c_uint64)]
+        L.mlp_create.argtypes = [i32, vp, C.c_uint64, vp, P(vp)]
+        L.mlp_destroy.argtypes = [vp]
+        L.mlp_set_params.argtypes = [vp, vp]
+        L.mlp_get_params.argtypes = [vp, vp]
+        L.mlp_forward.argtypes = [vp, i32, vp, vp]
+        L.mlp_backward.argtypes = [vp, i32, vp, vp, vp]
+        L.mlp_get_grads.argtypes = [vp, vp]
+        L.mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
+        L.mlp_last_error.restype = C.c_char_p
+        L.mlp_last_error.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -485,6 +499,116 @@ class Batch:
         if getattr(self, "b", None):
             pic_batch_destroy(self.b)
             self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- warm-start network, same names
+def _mcheck(code, h=None):
+    if code != PIC_OK:
+        msg = lib().mlp_last_error(h).decode() or lib().pic_strerror(code).decode()
+        raise PicError(code, msg)
+
+
+def mlp_query(max_batch):
+    n = C.c_uint64(0)
+    _mcheck(lib().mlp_query(int(max_batch), C.byref(n)))
+    return n.value
+
+
+def mlp_create(max_batch, workspace_ptr, nbytes, stream_ptr):
+    h = C.c_void_p()
+    _mcheck(lib().mlp_create(int(max_batch), C.c_void_p(workspace_ptr), nbytes, C.c_void_p(stream_ptr), C.byref(h)))
+    return h
+
+
+def mlp_destroy(h):
+    _mcheck(lib().mlp_destroy(h))
+
+
+def mlp_set_params(h, p):
+    a = np.ascontiguousarray(p, dtype=np.float32)
+    if a.size != MLP_NPARAM:
+        raise ValueError(f"need {MLP_NPARAM} parameters")
+    _mcheck(lib().mlp_set_params(h, _ptr(a)), h)
+
+
+def mlp_get_params(h):
+    a = np.zeros(MLP_NPARAM, np.float32)
+    _mcheck(lib().mlp_get_params(h, _ptr(a)), h)
+    return a
+
+
+def mlp_forward(h, batch, x_ptr, y_ptr):
+    _mcheck(lib().mlp_forward(h, int(batch), C.c_void_p(x_ptr), C.c_void_p(y_ptr)), h)
+
+
+def mlp_backward(h, batch, x_ptr, t_ptr, want_loss=True):
+    loss = C.c_float(0.0)
+    _mcheck(lib().mlp_backward(h, int(batch), C.c_void_p(x_ptr), C.c_void_p(t_ptr),
+                               C.byref(loss) if want_loss else None), h)
+    return loss.value if want_loss else None
+
+
+def mlp_get_grads(h):
+    a = np.zeros(MLP_NPARAM, np.float32)
+    _mcheck(lib().mlp_get_grads(h, _ptr(a)), h)
+    return a
+
+
+def mlp_adam(h, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    _mcheck(lib().mlp_adam(h, float(lr), float(beta1), float(beta2), float(eps)), h)
+
+
+class Network:
+    """The warm-start network on the current GPU (torch workspace and stream)."""
+
+    def __init__(self, max_batch, params=None, stream=None):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the network kernels run only on a gfx950 device")
+        self.max_batch = int(max_batch)
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        nbytes = mlp_query(self.max_batch)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.h = mlp_create(self.max_batch, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+        if params is not None:
+            self.set_params(params)
+
+    def set_params(self, p):
+        mlp_set_params(self.h, p)
+
+    def params(self):
+        return mlp_get_params(self.h)
+
+    def forward(self, x):
+        """x: float32 CUDA tensor [B][3] -> float32 CUDA tensor [B][6]."""
+        import torch
+        x = x.contiguous()
+        y = torch.empty((x.shape[0], 6), dtype=torch.float32, device=x.device)
+        for b0 in range(0, x.shape[0], self.max_batch):
+            b1 = min(x.shape[0], b0 + self.max_batch)
+            mlp_forward(self.h, b1 - b0, x[b0:b1].data_ptr(), y[b0:b1].data_ptr())
+        return y
+
+    def backward(self, x, t, want_loss=True):
+        x, t = x.contiguous(), t.contiguous()
+        return mlp_backward(self.h, x.shape[0], x.data_ptr(), t.data_ptr(), want_loss)
+
+    def grads(self):
+        return mlp_get_grads(self.h)
+
+    def adam(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        mlp_adam(self.h, lr, beta1, beta2, eps)
+
+    def close(self):
+        if getattr(self, "h", None):
+            mlp_destroy(self.h)
+            self.h = None
 
     def __del__(self):
         try:

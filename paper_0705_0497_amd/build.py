@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpicmcc.so")
-SOURCES = ["kernels.hip", "pic.cpp"]
+SOURCES = ["kernels.hip", "pic.cpp", "mlp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 # packed-FP32 instructions are switched off for every gfx950 code object

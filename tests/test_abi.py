@@ -13,9 +13,9 @@ from paper_0705_0497_amd import inputs as I
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
-def declared():
-    text = open(os.path.join(ROOT, "include", "pic.h")).read()
-    return sorted(set(re.findall(r"\b(pic_[a-z_]+)\s*\(", text)))
+def declared(header="pic.h", prefix="pic_"):
+    text = open(os.path.join(ROOT, "include", header)).read()
+    return sorted(set(re.findall(r"\b(" + prefix + r"[a-z_]+)\s*\(", text)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -26,6 +26,10 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), n
     assert set(names) == set(B.EXPORTS)
     assert lib.pic_version() >= 10000
+    mnames = declared("mlp.h", "mlp_")
+    assert set(mnames) == set(B.MLP_EXPORTS)
+    for n in mnames:
+        assert hasattr(lib, n), n
 
 
 def _args(d=None, procs=None, **kw):
@@ -126,3 +130,12 @@ def test_ksub_select_physics_valid_subcycling():
     assert B.pic_ksub_select(cfg, sp, 1e22, 0.0) == 1
     with pytest.raises(B.PicError):
         B.pic_ksub_select(cfg, sp, -1.0, 100.0)
+
+
+def test_mlp_query_sizes_and_limits():
+    small, big = B.mlp_query(1), B.mlp_query(4096)
+    assert small >= 18 * B.MLP_NPARAM                      # FP32 params, grads, moments + bf16 copy
+    assert big - small >= 4095 * (4 * 4 + 2 * 4) * 256     # pre-activations and activations per sample
+    for n in (0, (1 << 20) + 1):
+        with pytest.raises(B.PicError):
+            B.mlp_query(n)
