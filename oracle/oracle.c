@@ -298,6 +298,63 @@ void orc_load_uniform(orc_sim *S) {
   }
 }
 
+/* value of a piecewise-linear profile at x (x / L), constant beyond the end points */
+static double profile_at(int32_t n, const double *xs, const double *v, double x) {
+  if (x <= xs[0]) return v[0];
+  if (x >= xs[n - 1]) return v[n - 1];
+  int32_t k = 0;
+  while (xs[k + 1] <= x) ++k;
+  return v[k] + (v[k + 1] - v[k]) * (x - xs[k]) / (xs[k + 1] - xs[k]);
+}
+
+/* Warm-start loading.  Cell j (centre x_c = (j + 1/2) / ng) of species s is
+   given round(sum_{i <= j} e_i) - round(sum_{i < j} e_i) particles, e_i =
+   n_s(x_c) dx / w the expected number in cell i (rounding half up), with
+   offsets on the 2^24-point lattice of the cell and a Maxwellian at
+   T = (2/3) mean energy at x_c; particle k keeps the draws of uniform loading. */
+int orc_load_profile(orc_sim *S, int32_t n_pts, const double *xs, const double *dens, const double *mean_ev) {
+  if (n_pts < 2) return -1;
+  for (int32_t k = 0; k < n_pts; ++k) {
+    if (!(xs[k] >= 0.0 && xs[k] <= 1.0) || (k > 0 && !(xs[k] > xs[k - 1]))) return -1;
+    for (int s = 0; s < ORC_NSP; ++s) {
+      double d = dens[s * n_pts + k], e = mean_ev[s * n_pts + k];
+      if (!(isfinite(d) && d >= 0.0) || !(isfinite(e) && e > 0.0)) return -1;
+    }
+  }
+  int32_t ng = S->c.ng;
+  for (int s = 0; s < ORC_NSP; ++s) {
+    orc_store *a = &S->st[s];
+    a->n = 0;
+    double c = 0.0;
+    int64_t prev = 0;
+    for (int32_t j = 0; j < ng; ++j) {
+      double xc = ((double)j + 0.5) / (double)ng;
+      double n = profile_at(n_pts, xs, dens + s * n_pts, xc);
+      double t_ev = (2.0 / 3.0) * profile_at(n_pts, xs, mean_ev + s * n_pts, xc);
+      c += (n * S->dx) / S->c.weight;
+      int64_t cum = (int64_t)floor(c + 0.5);
+      double vth = sqrt(t_ev * Q_E / S->sp[s].mass);
+      store_reserve(a, cum);
+      for (int64_t k = prev; k < cum; ++k) {
+        int64_t i = store_push(a);
+        uint32_t id = (uint32_t)k, r0[4], r1[4];
+        draw(S, s, id, 0, ORC_P_LOAD, 0, r0);
+        draw(S, s, id, 0, ORC_P_LOAD, 1, r1);
+        a->xi[i] = (double)j + (double)(r0[0] >> 8) / 16777216.0;
+        double z0, z1, z2, z3;
+        normals(r1[0], r1[1], &z0, &z1);
+        normals(r1[2], r1[3], &z2, &z3);
+        a->vx[i] = vth * z0; a->vy[i] = vth * z1; a->vz[i] = vth * z2;
+        a->id[i] = id;
+        if (s == ORC_E) new_flight(S, r0[1], &a->cd[i], &a->capped[i], NULL);
+      }
+      prev = cum;
+    }
+    a->next_id = (uint32_t)prev;
+  }
+  return 0;
+}
+
 int orc_set_particles(orc_sim *S, int32_t s, int64_t n, const int32_t *cell, const float *off,
                       const float *vx, const float *vy, const float *vz, const uint32_t *id,
                       const int32_t *cdw, uint32_t next_id) {

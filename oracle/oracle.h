@@ -100,6 +100,10 @@ orc_sim *orc_create(const orc_config *cfg, const orc_species *sp, int32_t nproc,
 void orc_destroy(orc_sim *S);
 
 void orc_load_uniform(orc_sim *S);
+/* Loading from profiles (warm start): n_pts points x[k] (x / L, strictly
+   increasing in [0, 1]), densities dens[s][k] [m^-3] and mean energies
+   mean_ev[s][k] [eV] per species.  Returns 0, or -1 for an invalid profile. */
+int orc_load_profile(orc_sim *S, int32_t n_pts, const double *x, const double *dens, const double *mean_ev);
 int orc_set_particles(orc_sim *S, int32_t s, int64_t n, const int32_t *cell, const float *off,
                       const float *vx, const float *vy, const float *vz, const uint32_t *id,
                       const int32_t *cdw, uint32_t next_id);

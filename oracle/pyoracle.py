@@ -70,6 +70,8 @@ def lib():
         L.orc_create.argtypes = [C.POINTER(_Config), C.POINTER(_Species), i32, C.POINTER(_Process), vp]
         L.orc_destroy.argtypes = [vp]
         L.orc_load_uniform.argtypes = [vp]
+        L.orc_load_profile.argtypes = [vp, i32, vp, vp, vp]
+        L.orc_load_profile.restype = i32
         L.orc_set_particles.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, u32]
         L.orc_set_particles64.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, u32]
         L.orc_count.restype = i64
@@ -165,6 +167,14 @@ class Oracle:
 
     def load_uniform(self):
         lib().orc_load_uniform(self.h)
+
+    def load_profile(self, x, dens, mean_ev):
+        """Warm-start loading from profiles (x / L, densities [3][n], mean energies [3][n])."""
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        dens = np.ascontiguousarray(dens, dtype=np.float64)
+        mean_ev = np.ascontiguousarray(mean_ev, dtype=np.float64)
+        if lib().orc_load_profile(self.h, len(x), _p(x), _p(dens), _p(mean_ev)) != 0:
+            raise ValueError("invalid profile")
 
     def set_particles(self, s, st, next_id):
         n = len(st["id"])

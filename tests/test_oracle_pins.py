@@ -536,3 +536,64 @@ def test_resume_is_bitwise():
         oa, oc = np.argsort(pa["id"]), np.argsort(pc["id"])
         for k in ("xi", "vx", "vy", "vz", "id", "cd"):
             np.testing.assert_array_equal(pa[k][oa], pc[k][oc])
+
+
+def _profile_case(ng=64, n_total=40000):
+    d = I.config(1, ng=ng, n_total=n_total)
+    o = po.Oracle(d, d.species(), I.make_processes())
+    return d, o
+
+
+def test_profile_loading_counts_follow_the_density_integral():
+    d, o = _profile_case()
+    x = np.array([0.0, 0.3, 0.7, 1.0])
+    dens = np.array([[1e14, 5e14, 5e14, 1e14], [3e14, 1.2e15, 1.2e15, 3e14], [0.0, 2e14, 2e14, 0.0]])
+    mean = np.array([[2.0, 4.0, 4.0, 2.0], [0.05, 0.04, 0.04, 0.05], [0.04, 0.04, 0.04, 0.04]])
+    o.load_profile(x, dens, mean)
+    xc = (np.arange(d.ng) + 0.5) / d.ng
+    dx = d.L / d.ng
+    for s in range(3):
+        st = o.get_particles(s)
+        cells = np.floor(st["xi"]).astype(int)
+        counts = np.bincount(cells, minlength=d.ng)
+        expect = np.interp(xc, x, dens[s]) * dx / d.weight
+        cum_err = np.cumsum(counts) - np.cumsum(expect)
+        assert np.all(np.abs(cum_err) <= 0.5 + 1e-9), s          # cumulative rounding never drifts
+        assert np.all(np.abs(counts - expect) <= 1.0 + 1e-9)
+        assert sorted(st["id"].tolist()) == list(range(len(st["id"])))
+        assert o.next_id(s) == len(st["id"])
+        off = st["xi"] - cells
+        assert np.all((off >= 0) & (off < 1))
+        assert np.all(off * 2 ** 24 == np.floor(off * 2 ** 24))    # the 2^24 lattice of the cell
+
+
+def test_profile_loading_temperatures_follow_the_mean_energy():
+    d, o = _profile_case(ng=32, n_total=200000)
+    x = np.array([0.0, 1.0])
+    dens = np.array([[4e14, 4e14], [1e15, 1e15], [6e14, 6e14]])
+    mean = np.array([[1.5, 6.0], [0.06, 0.06], [0.03, 0.12]])
+    o.load_profile(x, dens, mean)
+    for s in (0, 2):
+        st = o.get_particles(s)
+        e = 0.5 * d.species()[s].mass * (st["vx"] ** 2 + st["vy"] ** 2 + st["vz"] ** 2) / QE
+        cells = np.floor(st["xi"]).astype(int)
+        for half, sel in (("left", cells < 8), ("right", cells >= 24)):
+            xc = (cells[sel] + 0.5) / d.ng
+            want = np.interp(xc, x, mean[s])
+            # mean kinetic energy of a 3D Maxwellian is (3/2) T = the profile's mean energy
+            ratio = e[sel] / want
+            sig = math.sqrt(2.0 / 3.0) / math.sqrt(sel.sum())         # std of a chi^2_3 / 3 mean
+            assert abs(ratio.mean() - 1.0) < 4 * sig, (s, half, ratio.mean())
+
+
+def test_profile_loading_rejects_invalid_profiles():
+    d, o = _profile_case(ng=16, n_total=3000)
+    good = (np.array([0.0, 1.0]), np.full((3, 2), 1e14), np.full((3, 2), 1.0))
+    for bad in ((np.array([0.0, 0.0]),) + good[1:],
+                (np.array([0.0, 1.5]),) + good[1:],
+                (good[0], np.array([[1e14, -1.0]] * 3), good[2]),
+                (good[0], good[1], np.array([[1.0, 0.0]] * 3)),
+                (good[0], np.array([[np.nan, 1.0]] * 3), good[2])):
+        with pytest.raises(ValueError):
+            o.load_profile(*bad)
+    o.load_profile(*good)
