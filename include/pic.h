@@ -45,6 +45,7 @@ extern "C" {
 #define PIC_ENAN (-5)          /* non-finite particle coordinate */
 #define PIC_EHIP (-6)          /* HIP runtime error */
 #define PIC_ENODEVICE (-7)     /* no usable gfx950 device */
+#define PIC_WFALLBACK 1        /* warning: invalid warm-start profile, loaded uniformly instead */
 
 /* process kinds (Table 1 channels handled by the library) */
 #define PIC_ELASTIC 0      /* e + O2 elastic (7) */
@@ -164,6 +165,24 @@ int pic_destroy(pic_handle *h);
    with ids 0..count-1 on the 2^24-point lattice of [0, L) and Maxwellian
    velocities at t0_ev, then pic_prepare(h, 1). */
 int pic_load_uniform(pic_handle *h);
+
+/* Warm start: loads every species from cycle-averaged profiles across the gap
+   (the quantities the paper reports in section 3: densities and mean energies
+   of e, O2+ and O-), e.g. predicted by the network of mlp.h.  n_pts points
+   x_over_L (strictly increasing in [0, 1]); dens [3][n_pts] [m^-3] and
+   mean_ev [3][n_pts] [eV] (> 0), host arrays, species order e, O2+, O-.
+   Profiles are linear between points and constant beyond the end points.
+   Cell j (centre x_c) of species s receives round(sum_{i<=j} e_i) -
+   round(sum_{i<j} e_i) particles, e_i = n_s(x_c) dx / weight (rounding half
+   up), ids 0..N_s-1 in cell order, offsets on the 2^24-point lattice of the
+   cell, Maxwellian velocities at T = (2/3) mean energy at x_c; the particle
+   draws are those of pic_load_uniform.  Then pic_prepare(h, 1), step 0.
+   Returns PIC_WFALLBACK (> 0) after loading uniformly when the profile is
+   invalid (too few points, x not increasing in [0, 1], a negative or
+   non-finite density, a non-positive mean energy); PIC_ECAPACITY if a
+   species needs more particles than its capacity. */
+int pic_load_profiles(pic_handle *h, int32_t n_pts, const double *x_over_L, const double *dens,
+                      const double *mean_ev);
 
 /* Canonical particle record exchanged with the host (arrays of n):
    cell in [0, ng), off in [0, 1) (x = (cell + off) L / ng), vx, vy, vz [m/s],

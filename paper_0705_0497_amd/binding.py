@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libpicmcc.so")
 
 PIC_OK, PIC_EINVAL, PIC_ECAPACITY, PIC_EIDOVERFLOW, PIC_ENAN, PIC_EHIP, PIC_ENODEVICE = 0, -1, -2, -3, -5, -6, -7
 PIC_EBUSY = -8
+PIC_WFALLBACK = 1
 TUNE_MAX = 32
 KIND = {"elastic": 0, "excite": 1, "ionize": 2, "attach": 3, "cx": 4, "neutralize": 5, "detach": 6}
 TARGET = {"O2": 0, "O2a": 1, "grid+": 2}
@@ -25,7 +26,8 @@ NBIN, NCOUNT = 256, 40
 C_PUSH, C_CAND, C_NULL, C_ABS0, C_ABSL, C_BORN, C_EVENT = 0, 3, 6, 9, 12, 15, 18
 C_PAIRED, C_DEFICIT, C_CLAMP, C_REDRAW = 34, 35, 36, 37
 
-EXPORTS = ("pic_version", "pic_query", "pic_create", "pic_destroy", "pic_load_uniform", "pic_set_particles",
+EXPORTS = ("pic_version", "pic_query", "pic_create", "pic_destroy", "pic_load_uniform", "pic_load_profiles",
+           "pic_set_particles",
            "pic_count", "pic_get_particles", "pic_prepare", "pic_set_step", "pic_get_step", "pic_step",
            "pic_sync", "pic_moments", "pic_get_hist", "pic_get_field", "pic_get_counters", "pic_get_events",
            "pic_nu_max", "pic_step_timed", "pic_strerror", "pic_last_error",
@@ -95,6 +97,7 @@ def lib():
         L.pic_create.argtypes = [P(pic_config), P(pic_species), P(pic_process), i32, vp, C.c_uint64, vp, P(vp)]
         L.pic_destroy.argtypes = [vp]
         L.pic_load_uniform.argtypes = [vp]
+        L.pic_load_profiles.argtypes = [vp, i32, vp, vp, vp]
         L.pic_set_particles.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, u32]
         L.pic_count.argtypes = [vp, i32, P(i64)]
         L.pic_get_particles.argtypes = [vp, i32, P(i64), vp, vp, vp, vp, vp, vp, vp, P(u32)]
@@ -209,6 +212,20 @@ def pic_destroy(h):
 
 def pic_load_uniform(h):
     _check(lib().pic_load_uniform(h), h)
+
+
+def pic_load_profiles(h, x, dens, mean_ev):
+    """Returns True if the profile was used, False after the uniform fallback."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    dens = np.ascontiguousarray(dens, dtype=np.float64)
+    mean_ev = np.ascontiguousarray(mean_ev, dtype=np.float64)
+    if dens.shape != (3, len(x)) or mean_ev.shape != (3, len(x)):
+        raise ValueError("dens and mean_ev must be [3][n_pts]")
+    code = lib().pic_load_profiles(h, len(x), _ptr(x), _ptr(dens), _ptr(mean_ev))
+    if code == PIC_WFALLBACK:
+        return False
+    _check(code, h)
+    return True
 
 
 def pic_set_particles(h, s, st, next_id):
@@ -349,6 +366,9 @@ class Discharge:
 
     def load_uniform(self):
         pic_load_uniform(self.h)
+
+    def load_profiles(self, x, dens, mean_ev):
+        return pic_load_profiles(self.h, x, dens, mean_ev)
 
     def set_particles(self, s, st, next_id):
         pic_set_particles(self.h, s, st, next_id)

@@ -1175,6 +1175,34 @@ __global__ __launch_bounds__(BS) void k_load(Sim S, int s, int64_t count, float 
   }
 }
 
+// warm-start loading: particle k of species s goes to the cell j with
+// cum[j-1] <= k < cum[j], at a lattice offset, Maxwellian at vth[j]
+template <int BS>
+__global__ __launch_bounds__(BS) void k_load_profile(Sim S, int s, int64_t count, const long long *cum,
+                                                     const float *vth) {
+  const Particles &P = S.p[s];
+  const int ng = S.ng;
+  for (int64_t k = (int64_t)blockIdx.x * BS + threadIdx.x; k < count; k += (int64_t)gridDim.x * BS) {
+    int lo = 0, hi = ng - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (cum[mid] > k) hi = mid;
+      else lo = mid + 1;
+    }
+    const uint32_t id = (uint32_t)k;
+    const U4 r0 = draw(S, s, id, 0, P_LOAD, 0);
+    const U4 r1 = draw(S, s, id, 0, P_LOAD, 1);
+    const float off = (float)(r0.x >> 8) * 0x1p-24f;
+    float z0, z1, z2, z3;
+    normals(r1.x, r1.y, z0, z1);
+    normals(r1.z, r1.w, z2, z3);
+    const float v = vth[lo];
+    const int32_t w = s == 0 ? (lo | (int32_t)new_flight(S.nd_e, r0.y)) : lo;
+    put(P, k, w, off, v * z0, v * z1, v * z2);
+    P.id[k] = id;
+  }
+}
+
 template <int BS>
 __global__ __launch_bounds__(BS) void k_shift(Sim S, int s) {
   const Particles &P = S.p[s];
@@ -1451,6 +1479,12 @@ hipError_t launch_diag(const Sim &S, int s, int grid, hipStream_t st) {
 
 hipError_t launch_load(const Sim &S, int s, int64_t count, float vth, int grid, hipStream_t st) {
   hipLaunchKernelGGL((k_load<GBS>), dim3(grid), dim3(GBS), 0, st, S, s, count, vth);
+  return hipGetLastError();
+}
+
+hipError_t launch_load_profile(const Sim &S, int s, int64_t count, const long long *cum, const float *vth, int grid,
+                               hipStream_t st) {
+  hipLaunchKernelGGL((k_load_profile<GBS>), dim3(grid), dim3(GBS), 0, st, S, s, count, cum, vth);
   return hipGetLastError();
 }
 

@@ -23,6 +23,8 @@ hipError_t launch_sort(const Sim &S, int s, const Particles &dst, int grid, hipS
 hipError_t launch_diag(const Sim &S, int s, int grid, hipStream_t st);
 hipError_t launch_load(const Sim &S, int s, int64_t count, float vth, int grid, hipStream_t st);
 hipError_t launch_shift(const Sim &S, int s, int grid, hipStream_t st);
+hipError_t launch_load_profile(const Sim &S, int s, int64_t count, const long long *cum, const float *vth, int grid,
+                               hipStream_t st);
 hipError_t launch_deposit(const Sim &S, int s, int grid, hipStream_t st);
 hipError_t set_lds_limits(const Sim &S, int block);
 hipError_t launch_reduce(const Sim &S, int s, int push_grid, hipStream_t st);
@@ -57,7 +59,7 @@ struct Layout {
   size_t part[NSP][2][6];   // two buffers x (w, off, vx, vy, vz, id)
   size_t pkey[NSP], pbkt[NSP], ptmp[NSP], bcnt;
   size_t Q, E, phi, sumQ, sumphi, esum, ecnt, edf, iedf, nacc, kleft, cmin, sortcnt, sortbase, sc, sigma,
-      hbound, events, partials, ttot, blkcnt;
+      hbound, events, partials, ttot, blkcnt, prof;
   size_t take(size_t bytes) {
     const size_t o = total;
     total += (bytes + 255) & ~(size_t)255;
@@ -98,6 +100,7 @@ Layout make_layout(const pic_config &c, const pic_species *sp, int nproc) {
   L.partials = L.take(8 * nn * (size_t)(c.grid > 0 ? c.grid : max_push_grid()));
   L.ttot = L.take(4 * (size_t)c.table_n);
   L.blkcnt = L.take(8 * 4096);
+  L.prof = L.take((8 + 4) * NSP * (size_t)c.ng);   // warm-start loading: per-cell cumulative counts, speeds
   return L;
 }
 
@@ -499,6 +502,96 @@ int pic_load_uniform(pic_handle *h) {
     unsigned long long n = (unsigned long long)h->sp[s].count, z = 0;
     uint32_t nid = (uint32_t)h->sp[s].count;
     int r = set_scalar(h, offsetof(Scalars, n) + 8 * s, &n, 8);
+    if (r == PIC_OK) r = set_scalar(h, offsetof(Scalars, nnew) + 8 * s, &z, 8);
+    if (r == PIC_OK) r = set_scalar(h, offsetof(Scalars, next_id) + 4 * s, &nid, 4);
+    if (r != PIC_OK) return r;
+  }
+  h->step = 0;
+  return pic_prepare(h, 1);
+}
+
+}  // extern "C"
+
+namespace {
+
+// piecewise-linear profile at x (x / L), constant beyond the end points
+#pragma clang fp contract(off)
+double profile_at(int32_t n, const double *xs, const double *v, double x) {
+  if (x <= xs[0]) return v[0];
+  if (x >= xs[n - 1]) return v[n - 1];
+  int32_t k = 0;
+  while (xs[k + 1] <= x) ++k;
+  return v[k] + (v[k + 1] - v[k]) * (x - xs[k]) / (xs[k + 1] - xs[k]);
+}
+
+bool valid_profile(int32_t n, const double *xs, const double *dens, const double *mean_ev) {
+  if (n < 2 || !xs || !dens || !mean_ev) return false;
+  for (int32_t k = 0; k < n; ++k) {
+    if (!(xs[k] >= 0.0 && xs[k] <= 1.0) || (k > 0 && !(xs[k] > xs[k - 1]))) return false;
+    for (int s = 0; s < NSP; ++s) {
+      const double d = dens[s * n + k], e = mean_ev[s * n + k];
+      if (!(std::isfinite(d) && d >= 0.0) || !(std::isfinite(e) && e > 0.0)) return false;
+    }
+  }
+  return true;
+}
+
+// cumulative counts round(sum_{i <= j} n(x_i) dx / w) and thermal speeds per cell
+#pragma clang fp contract(off)
+void profile_counts(const pic_handle *h, int s, int32_t n, const double *xs, const double *dens,
+                    const double *mean_ev, std::vector<long long> &cum, std::vector<float> &vth) {
+  const int32_t ng = h->cfg.ng;
+  const double dx = h->cfg.L / ng;
+  cum.resize(ng);
+  vth.resize(ng);
+  double c = 0.0;
+  for (int32_t j = 0; j < ng; ++j) {
+    const double xc = ((double)j + 0.5) / (double)ng;
+    const double nd = profile_at(n, xs, dens + s * n, xc);
+    const double t_ev = (2.0 / 3.0) * profile_at(n, xs, mean_ev + s * n, xc);
+    c += (nd * dx) / h->cfg.weight;
+    cum[j] = (long long)std::floor(c + 0.5);
+    vth[j] = (float)std::sqrt(t_ev * QE / h->sp[s].mass);
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+int pic_load_profiles(pic_handle *h, int32_t n_pts, const double *x_over_L, const double *dens,
+                      const double *mean_ev) {
+  if (!h) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
+  if (!valid_profile(n_pts, x_over_L, dens, mean_ev)) {
+    const int r = pic_load_uniform(h);
+    if (r != PIC_OK) return r;
+    h->err = "invalid profile: loaded uniformly instead";
+    return PIC_WFALLBACK;
+  }
+  std::vector<long long> cum[NSP];
+  std::vector<float> vth[NSP];
+  for (int s = 0; s < NSP; ++s) {
+    profile_counts(h, s, n_pts, x_over_L, dens, mean_ev, cum[s], vth[s]);
+    if (cum[s].back() > h->sp[s].capacity) return fail(h, PIC_ECAPACITY, "profile needs more particles than the capacity");
+  }
+  HIPCHK(h, launch_fixup(h->S, h->stream));        // settle products still waiting for ids
+  HIPCHK(h, hipStreamSynchronize(h->stream));
+  const size_t ng = h->cfg.ng;
+  long long *dcum = (long long *)(h->ws + h->L.prof);
+  float *dvth = (float *)(h->ws + h->L.prof + 8 * NSP * ng);
+  for (int s = 0; s < NSP; ++s) {
+    HIPCHK(h, hipMemcpy(dcum + s * ng, cum[s].data(), 8 * ng, hipMemcpyHostToDevice));
+    HIPCHK(h, hipMemcpy(dvth + s * ng, vth[s].data(), 4 * ng, hipMemcpyHostToDevice));
+  }
+  for (int s = 0; s < NSP; ++s) {
+    h->cur[s] = 0;
+    h->S.p[s] = h->buf[s][0];
+    const long long count = cum[s].back();
+    if (count > 0) HIPCHK(h, launch_load_profile(h->S, s, count, dcum + s * ng, dvth + s * ng, h->hgrid, h->stream));
+    unsigned long long nn = (unsigned long long)count, z = 0;
+    uint32_t nid = (uint32_t)count;
+    int r = set_scalar(h, offsetof(Scalars, n) + 8 * s, &nn, 8);
     if (r == PIC_OK) r = set_scalar(h, offsetof(Scalars, nnew) + 8 * s, &z, 8);
     if (r == PIC_OK) r = set_scalar(h, offsetof(Scalars, next_id) + 4 * s, &nid, 4);
     if (r != PIC_OK) return r;

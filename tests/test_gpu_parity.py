@@ -307,3 +307,48 @@ def test_full_size_sampled_single_step(cfg):
             dx, dv = H.compare_states(gs, os_, d.species()[s], skip=band, s=s)
             assert dx <= H.POS_TOL and dv <= H.VEL_TOL, (cfg, step_kind, s, dx, dv)
         g.sync()
+
+
+def _profile():
+    x = np.linspace(0.0, 1.0, 17)
+    bump = np.sin(np.pi * x)
+    dens = np.stack([2e14 + 4e14 * bump, 3e14 + 9e14 * bump, 1e14 + 5e14 * bump ** 2])
+    mean = np.stack([1.0 + 3.0 * bump, 0.04 + 0.5 * x, np.full_like(x, 0.039)])
+    return x, dens, mean
+
+
+def test_profile_loader_matches_oracle():
+    from paper_0705_0497_amd.binding import Discharge
+    d = I.config(1, n_total=60000)
+    procs = I.make_processes()
+    x, dens, mean = _profile()
+    o = po.Oracle(d, d.species(), procs)
+    o.load_profile(x, dens, mean)
+    o.prepare(True)
+    g = Discharge(d, procs)
+    assert g.load_profiles(x, dens, mean)
+    for s in range(3):
+        gs, os_ = g.get_particles(s)[0], o.get_particles(s)
+        assert len(gs["id"]) == len(os_["id"]) > 1000
+        dx, dv = H.compare_states(gs, os_, d.species()[s], s=s)
+        assert dx == 0.0 and dv < 1e-5, (s, dx, dv)                 # same cells, same lattice offsets
+    np.testing.assert_array_equal(g.hist(), o.hist())
+    phi_g, _ = g.field()
+    phi_o, _ = o.field()
+    assert np.max(np.abs(phi_g - phi_o)) <= 1e-12 * np.max(np.abs(phi_o))
+
+
+def test_profile_loader_falls_back_to_uniform_on_invalid_input():
+    from paper_0705_0497_amd.binding import Discharge
+    d = I.config(1)
+    procs = I.make_processes()
+    x, dens, mean = _profile()
+    mean[0, 3] = -1.0                                                 # a negative mean energy
+    g = Discharge(d, procs)
+    assert g.load_profiles(x, dens, mean) is False
+    u = Discharge(d, procs)
+    u.load_uniform()
+    for s in range(3):
+        a, b = H.by_id(g.get_particles(s)[0]), H.by_id(u.get_particles(s)[0])
+        for k in ("cell", "off", "vx", "vy", "vz", "id", "cd"):
+            np.testing.assert_array_equal(a[k], b[k])
