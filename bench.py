@@ -83,8 +83,11 @@ def main():
     ap.add_argument("--sort", choices=("compact", "cell"), default="compact",
                     help="periodic re-ordering: order-preserving compaction or counting sort by cell")
     ap.add_argument("--sort-every", type=int, default=2000)
-    ap.add_argument("--workload", choices=("single", "sweep"), default="single",
-                    help="single: the 4096-cell discharge; sweep: 64 discharges advanced as one batch")
+    ap.add_argument("--workload", choices=("single", "sweep", "warmstart"), default="single",
+                    help="single: the 4096-cell discharge; sweep: 64 discharges advanced as one batch; "
+                         "warmstart: learned warm start against cold starts")
+    ap.add_argument("--train-runs", type=int, default=64, help="warmstart: training discharges")
+    ap.add_argument("--test-runs", type=int, default=16, help="warmstart: held-out discharges")
     ap.add_argument("--members", type=int, default=64, help="sweep: discharges in the batch")
     ap.add_argument("--tune-window", type=int, default=200, help="sweep: autotuner trial length [steps]")
     args = ap.parse_args()
@@ -101,6 +104,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "sweep":
         return sweep(args)
+    if args.workload == "warmstart":
+        return warmstart(args)
     d = I.config(3)
     procs = I.make_processes()
     log(f"bench: loading {d.name} ({sum(d.species_counts())} superparticles, {d.ng} cells)")
@@ -251,6 +256,50 @@ def sweep(args):
     }
     print(json.dumps(out), flush=True)
     b.close()
+
+
+def warmstart(args):
+    """Learned warm start: training profiles from batched cold runs to
+    convergence, the network trained on the GPU, then every held-out (U, p)
+    run cold and warm in one batch until its convergence test holds.  value =
+    particle-steps/s of that evaluation batch; the rf cycles to steady state,
+    cold and warm, and the profile errors are in config."""
+    import numpy as np
+    from paper_0705_0497_amd import warmstart as W
+    t0 = time.perf_counter()
+    r = W.experiment(W.sample_points(args.train_runs, 11), W.sample_points(args.test_runs, 12),
+                     n_total=100000, max_cycles=2000, epochs=1500, reference=True,
+                     log=lambda m: log(f"bench: [{time.perf_counter() - t0:5.0f} s] {m}"))
+    rows = r["rows"]
+    cold = [x["cold_cycles"] for x in rows]
+    warm = [x["warm_cycles"] for x in rows]
+    both = [(c, w) for c, w in zip(cold, warm) if c is not None and w is not None]
+    err = np.array([x["density_error"] for x in rows])
+    out = {
+        "metric": "particle-steps/s (push+deposit+MCC); rf cycles to steady state, warm vs cold",
+        "value": r["pushes"]["eval"] / r["seconds"]["eval"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": r["eval_cycles"], "warmup": 0,
+        "ms_per_step": 1e3 * r["seconds"]["eval"] / r["eval_cycles"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+        "config": {"workload": f"learned warm start: {args.train_runs} training + {args.test_runs} held-out "
+                               "128-cell O2 CCP discharges (L=2.5 cm, U 150-350 V, p 15-40 Pa, 1e5 superparticles)",
+                   "step": "one rf cycle of the evaluation batch (cold and warm members together)",
+                   "cycles_cold": cold, "cycles_warm": warm,
+                   "cycles_ratio_total": sum(c for c, _ in both) / max(1, sum(w for _, w in both)),
+                   "cycles_ratio_median": float(np.median([c / w for c, w in both])) if both else None,
+                   "density_error_median": {"e": float(np.median(err[:, 0])), "O2+": float(np.median(err[:, 1])),
+                                            "O-": float(np.median(err[:, 2]))},
+                   "density_error_max": {"e": float(err[:, 0].max()), "O2+": float(err[:, 1].max()),
+                                         "O-": float(err[:, 2].max())},
+                   "within_5pct_e_and_O2+": int(sum(1 for x in rows if max(x["density_error"][:2]) < 0.05)),
+                   "cold_vs_cold_error_median": {k: float(np.median([x["reference_density_error"][s] for x in rows]))
+                                                 for s, k in enumerate(("e", "O2+", "O-"))},
+                   "points": [{k: v for k, v in x.items()} for x in rows],
+                   "train_converged_cycles": r["train_converged"], "loss_first_last": [r["loss"][0], r["loss"][-1]],
+                   "seconds": r["seconds"], "parallelism": "single GPU"},
+    }
+    print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":

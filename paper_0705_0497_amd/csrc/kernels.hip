@@ -191,8 +191,11 @@ __device__ T block_exclusive_scan(T v, T *buf, T &total) {
 // phi[ng] = 0.  Written as D[j+1/2] = D[1/2] + sum_{m=1..j} rho[m] dx (exact int64
 // prefix of the node charges), phi[j] = phi0 - (dx/eps0) sum_{m<j} D[m+1/2]; phi[ng] = 0
 // fixes D[1/2].  Same linear system as the tridiagonal one, solved by two scans.
+constexpr int FIELD_PER = 9;   // nodes per thread of the field block: (8192 + 1) / 1024 rounded up
+
 template <int BS>
 __device__ void field_block(const Sim &S, int64_t step, int mode) {
+  static_assert(BS * FIELD_PER >= 8193, "the field block holds every node of the largest grid");
   __shared__ long long sI[BS];
   __shared__ double sJ[BS];
   const int ng = S.ng, nn = ng + 1, t = threadIdx.x;
@@ -200,18 +203,29 @@ __device__ void field_block(const Sim &S, int64_t step, int mode) {
   const int j0 = min(t * per, nn), j1 = min(j0 + per, nn);
   const bool ion = (step % S.ksub) == 0;
   const unsigned long long *Qe = S.Q, *Qp = S.Q + nn, *Qn = S.Q + 2 * nn;
+  // this thread's node charges, read once: q_j = sum_s charge_s Q_s,j (fixed point)
+  unsigned long long qe[FIELD_PER], qp[FIELD_PER], qn[FIELD_PER];
+  long long q[FIELD_PER];
+#pragma unroll
+  for (int u = 0; u < FIELD_PER; ++u) {
+    const int j = j0 + u;
+    qe[u] = qp[u] = qn[u] = 0ull;
+    if (j < j1) { qe[u] = Qe[j]; qp[u] = Qp[j]; qn[u] = Qn[j]; }
+    q[u] = (long long)S.charge[0] * (long long)qe[u] + (long long)S.charge[1] * (long long)qp[u] +
+           (long long)S.charge[2] * (long long)qn[u];
+  }
   if (S.flags & F_EXT_FIELD) {
     for (int j = j0; j < j1; ++j) {
       S.E[j] = (float)(S.e_ext0 + S.e_ext1 * ((double)j * S.dx - 0.5 * S.L));
       S.phi[j] = 0.0;
     }
   }
-  // node charge q_j in fixed point; the interior part enters the first scan
+  // the interior charges enter the first scan
   long long loc = 0;
-  for (int j = j0; j < j1; ++j) {
-    const long long q = (long long)S.charge[0] * (long long)Qe[j] + (long long)S.charge[1] * (long long)Qp[j] +
-                        (long long)S.charge[2] * (long long)Qn[j];
-    if (j > 0 && j < ng) loc += q;
+#pragma unroll
+  for (int u = 0; u < FIELD_PER; ++u) {
+    const int j = j0 + u;
+    if (j < j1 && j > 0 && j < ng) loc += q[u];
   }
   long long itot;
   const long long ibase = block_exclusive_scan<BS, long long>(loc, sI, itot);
@@ -219,15 +233,17 @@ __device__ void field_block(const Sim &S, int64_t step, int mode) {
   double jloc = 0.0;
   {
     long long run = ibase;
-    for (int j = j0; j < j1; ++j) {
-      const long long q = (long long)S.charge[0] * (long long)Qe[j] + (long long)S.charge[1] * (long long)Qp[j] +
-                          (long long)S.charge[2] * (long long)Qn[j];
-      if (j > 0 && j < ng) run += q;
+#pragma unroll
+    for (int u = 0; u < FIELD_PER; ++u) {
+      const int j = j0 + u;
+      if (j >= j1) break;
+      if (j > 0 && j < ng) run += q[u];
       if (j < ng) jloc += (double)run;
     }
   }
   double jtot;
   const double jbase = block_exclusive_scan<BS, double>(jloc, sJ, jtot);
+  double phiv[FIELD_PER];
   if (!(S.flags & F_EXT_FIELD)) {
     const double c = S.qcharge;            // e w 2^-32: charge per unit area per fixed-point unit
     const double phi0 = S.U * sin(2.0 * M_PI * S.f * ((double)step * S.dt));
@@ -235,28 +251,37 @@ __device__ void field_block(const Sim &S, int64_t step, int mode) {
     const double k = S.dx / S.eps0;
     long long run = ibase;
     double jrun = jbase;
-    for (int j = j0; j < j1; ++j) {
-      const long long q = (long long)S.charge[0] * (long long)Qe[j] + (long long)S.charge[1] * (long long)Qp[j] +
-                          (long long)S.charge[2] * (long long)Qn[j];
+#pragma unroll
+    for (int u = 0; u < FIELD_PER; ++u) {
+      const int j = j0 + u;
+      phiv[u] = 0.0;
+      if (j >= j1) break;
       const long long iprev = run;                 // I_{j-1}
-      if (j > 0 && j < ng) run += q;               // I_j
+      if (j > 0 && j < ng) run += q[u];            // I_j
       const double phi = (j == ng) ? 0.0 : phi0 - k * ((double)j * d_half + c * jrun);
       double e;
-      if (j == 0) e = (d_half - c * (double)q) / S.eps0;
-      else if (j == ng) e = (d_half + c * (double)iprev + c * (double)q) / S.eps0;
+      if (j == 0) e = (d_half - c * (double)q[u]) / S.eps0;
+      else if (j == ng) e = (d_half + c * (double)iprev + c * (double)q[u]) / S.eps0;
       else e = (2.0 * d_half + c * ((double)iprev + (double)run)) / (2.0 * S.eps0);
       S.phi[j] = phi;
       S.E[j] = (float)e;
+      phiv[u] = phi;
       if (j < ng) jrun += (double)run;
     }
+  } else {
+#pragma unroll
+    for (int u = 0; u < FIELD_PER; ++u) phiv[u] = 0.0;
   }
   if (mode != 0) return;
   // cycle sums of the state this solve saw, then clear what this step rebuilds
-  for (int j = j0; j < j1; ++j) {
-    S.sumQ[j] += (double)Qe[j];
-    S.sumQ[nn + j] += (double)Qp[j];
-    S.sumQ[2 * nn + j] += (double)Qn[j];
-    S.sumphi[j] += S.phi[j];
+#pragma unroll
+  for (int u = 0; u < FIELD_PER; ++u) {
+    const int j = j0 + u;
+    if (j >= j1) break;
+    S.sumQ[j] += (double)qe[u];
+    S.sumQ[nn + j] += (double)qp[u];
+    S.sumQ[2 * nn + j] += (double)qn[u];
+    S.sumphi[j] += phiv[u];
     S.Q[j] = 0ull;
     if (ion) { S.Q[nn + j] = 0ull; S.Q[2 * nn + j] = 0ull; }
   }
@@ -421,41 +446,47 @@ __device__ __forceinline__ Cand load_cand(const Particles &P, int64_t i) {
   return c;
 }
 
-// electron collision at the end of a free flight (post-push state in q)
+// upper bound of the electron collision rate at energy ec over nu_max, times the
+// relative speed g: most free-flight ends fall above it and are null collisions
+__device__ __forceinline__ float electron_bound(const PushShared &sh, TabPos tp, float g) {
+  return fmaf(tp.w, sh.ttot[tp.i + 1] - sh.ttot[tp.i], sh.ttot[tp.i]) * g;
+}
+
+// energy of an electron for the tables: clamped into [emin, emax], and the speed
+// that goes with the clamped energy
+struct ECand { float e, ec, g; bool clamped; };
+
+__device__ __forceinline__ ECand electron_energy(const Sim &S, float v2) {
+  ECand r;
+  r.e = S.half_m_e[0] * v2;
+  r.ec = r.e;
+  r.clamped = false;
+  if (r.ec < S.emin) { r.ec = S.emin; r.clamped = true; }
+  else if (r.ec > S.emax) { r.ec = S.emax; r.clamped = true; }
+  r.g = r.clamped ? sqrtf(S.two_e_m[0] * r.ec) : sqrtf(v2);
+  return r;
+}
+
+// Electron whose free flight ended this step and whose draw fell below the
+// rate bound: the channel is chosen from the tables; the new free flight is
+// already in its cell word (post-push state in q).
 __device__ void collide_electron(const Sim &S, int64_t step, const Cand &q, PushShared sh, BlockCounts &bc,
                                  ThreadCounts &tc) {
   const Particles &P = S.p[0];
   const int64_t i = q.i;
-  const int32_t w = q.w;
   const float off = q.off;
   const uint32_t id = q.id;
   const float vx = q.vx, vy = q.vy, vz = q.vz;
-  const int cell = w & (int32_t)W_CELL;
+  const int cell = q.w & (int32_t)W_CELL;
   const U4 c = draw(S, 0, id, step, P_CAND, 0);
-  const uint32_t flight = new_flight_f(S.inv_nd_ef, c.x);
-  if (w & (int32_t)W_CAP) {                    // capped flight: redraw, no collision
-    P.w[i] = cell | (int32_t)flight;
-    dep_lds(sh.Q, cell, off);
-    count_lanes(bc, C_REDRAW);
-    log_event(S, step, 0, id, -2);
-    return;
-  }
-  ++tc.cand;
   const float v2 = vx * vx + vy * vy + vz * vz;
-  const float e = S.half_m_e[0] * v2;
-  float ec = e;
-  bool cl = false;
-  if (ec < S.emin) { ec = S.emin; cl = true; }
-  else if (ec > S.emax) { ec = S.emax; cl = true; }
-  if (cl) count_lanes(bc, C_CLAMP);
-  const float g = cl ? sqrtf(S.two_e_m[0] * ec) : sqrtf(v2);
+  const ECand en = electron_energy(S, v2);
+  const float e = en.e, ec = en.ec, g = en.g;
   const TabPos tp = tab_pos(S, ec);
   const float target = unif(c.y);
   int chosen = -1, kind = 0;
   float eth = 0.0f, tmr = 0.0f;
-  // upper bound of the total collision frequency: most candidates are null
-  const float bound = fmaf(tp.w, sh.ttot[tp.i + 1] - sh.ttot[tp.i], sh.ttot[tp.i]) * g;
-  if (target < bound * 1.000001f) {
+  {
     float acc = 0.0f;
     const int np = S.nproc_sp[0];
     for (int k = 0; k < np; ++k) {
@@ -467,7 +498,6 @@ __device__ void collide_electron(const Sim &S, int64_t step, const Cand &q, Push
   }
   log_event(S, step, 0, id, chosen);
   if (chosen < 0) {
-    P.w[i] = cell | (int32_t)flight;
     dep_lds(sh.Q, cell, off);
     ++tc.nul;
     return;
@@ -517,7 +547,6 @@ __device__ void collide_electron(const Sim &S, int64_t step, const Cand &q, Push
     return;
   }
   const float vn = sqrtf(S.two_e_m[0] * fmaxf(enew, 0.0f));
-  P.w[i] = cell | (int32_t)flight;
   P.vx[i] = vn * d0;
   P.vy[i] = vn * d1;
   P.vz[i] = vn * d2;
@@ -601,7 +630,7 @@ __device__ __forceinline__ int64_t push_chunk(int64_t N, int grid) {
 }
 
 #ifndef PICMCC_PUSH_WAVES
-#define PICMCC_PUSH_WAVES 1
+#define PICMCC_PUSH_WAVES 4
 #endif
 // block-level LDS state of a push run besides the dynamic part
 struct PushLds {
@@ -659,7 +688,7 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
     if (i0 < end) {
       const int nv = (int)min((int64_t)GROUP, end - i0);
       int32_t w[GROUP];
-      float off[GROUP], vx[GROUP];
+      float off[GROUP], vx[GROUP], vy[GROUP], vz[GROUP];
       uint32_t id[GROUP];
       {
         const int4 wa = *reinterpret_cast<const int4 *>(P.w + i0), wb = *reinterpret_cast<const int4 *>(P.w + i0 + 4);
@@ -668,9 +697,17 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
         w[0] = wa.x; w[1] = wa.y; w[2] = wa.z; w[3] = wa.w; w[4] = wb.x; w[5] = wb.y; w[6] = wb.z; w[7] = wb.w;
         off[0] = oa.x; off[1] = oa.y; off[2] = oa.z; off[3] = oa.w; off[4] = ob.x; off[5] = ob.y; off[6] = ob.z; off[7] = ob.w;
         vx[0] = va.x; vx[1] = va.y; vx[2] = va.z; vx[3] = va.w; vx[4] = vb.x; vx[5] = vb.y; vx[6] = vb.z; vx[7] = vb.w;
-        if (S_ != 0 && !nocoll && pnull > 0.0) {
+        if (S_ == 0 || (!nocoll && pnull > 0.0)) {
           const uint4 ia = *reinterpret_cast<const uint4 *>(P.id + i0), ib = *reinterpret_cast<const uint4 *>(P.id + i0 + 4);
           id[0] = ia.x; id[1] = ia.y; id[2] = ia.z; id[3] = ia.w; id[4] = ib.x; id[5] = ib.y; id[6] = ib.z; id[7] = ib.w;
+        }
+        if (S_ == 0) {
+          // electrons: every cache line of the cold fields is needed anyway (a third of the
+          // particles end a free flight each step), so they stream in with the hot ones
+          const float4 ya = *reinterpret_cast<const float4 *>(P.vy + i0), yb = *reinterpret_cast<const float4 *>(P.vy + i0 + 4);
+          const float4 za = *reinterpret_cast<const float4 *>(P.vz + i0), zb = *reinterpret_cast<const float4 *>(P.vz + i0 + 4);
+          vy[0] = ya.x; vy[1] = ya.y; vy[2] = ya.z; vy[3] = ya.w; vy[4] = yb.x; vy[5] = yb.y; vy[6] = yb.z; vy[7] = yb.w;
+          vz[0] = za.x; vz[1] = za.y; vz[2] = za.z; vz[3] = za.w; vz[4] = zb.x; vz[5] = zb.y; vz[6] = zb.z; vz[7] = zb.w;
         }
       }
 #pragma unroll
@@ -695,8 +732,8 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
         off[k] = no;
         if (nc < 0 || nc >= ng) {                      // absorbed by an electrode
           const int side = nc < 0 ? 0 : 1;
-          const float vy = P.vy[i0 + k], vz = P.vz[i0 + k];
-          const float en = S.half_m_e[S_] * (v * v + vy * vy + vz * vz);
+          const float uy = S_ == 0 ? vy[k] : P.vy[i0 + k], uz = S_ == 0 ? vz[k] : P.vz[i0 + k];
+          const float en = S.half_m_e[S_] * (v * v + uy * uy + uz * uz);
           atomicAdd(&wall.iedf[side][ebin(en)], 1u);
           atomicAdd(&bc.c[(side ? C_ABSL : C_ABS0) + S_], 1u);
           w[k] = W_DEAD;
@@ -706,9 +743,31 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
         if (S_ == 0) {
           const int cd = w[k] >> W_CD_SHIFT;
           const int cdn = nocoll ? cd : cd - 1;
-          w[k] = nc | (w[k] & (int32_t)W_CAP) | (cdn << W_CD_SHIFT);
-          if (cdn > 0 || nocoll) run.add(sh.Q, nc, no);
-          else cmask |= 1u << k;
+          if (cdn > 0 || nocoll) {
+            w[k] = nc | (w[k] & (int32_t)W_CAP) | (cdn << W_CD_SHIFT);
+            run.add(sh.Q, nc, no);
+          } else {                                     // the free flight ends: draw the next one
+            const U4 c = draw(S, 0, id[k], step, P_CAND, 0);
+            const bool capped = (w[k] & (int32_t)W_CAP) != 0;
+            w[k] = nc | (int32_t)new_flight_f(S.inv_nd_ef, c.x);
+            if (capped) {                              // end of a capped flight: no collision
+              run.add(sh.Q, nc, no);
+              count_lanes(bc, C_REDRAW);
+              if (S.event_cap > 0) log_event(S, step, 0, id[k], -2);
+            } else {
+              ++tc.cand;
+              const ECand en = electron_energy(S, v * v + vy[k] * vy[k] + vz[k] * vz[k]);
+              if (en.clamped) count_lanes(bc, C_CLAMP);
+              const TabPos tp = tab_pos(S, en.ec);
+              if (unif(c.y) < electron_bound(sh, tp, en.g) * 1.000001f) {
+                cmask |= 1u << k;                      // may collide: channel chosen by the block
+              } else {                                 // null collision
+                run.add(sh.Q, nc, no);
+                ++tc.nul;
+                if (S.event_cap > 0) log_event(S, step, 0, id[k], -1);
+              }
+            }
+          }
         } else {
           w[k] = nc;
           bool cand = false;

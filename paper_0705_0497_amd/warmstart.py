@@ -239,10 +239,11 @@ def sample_points(n, seed, U=(150.0, 350.0), p=(15.0, 40.0)):
     return [(float(a), float(b)) for a, b in zip(Us, ps)]
 
 
-def experiment(train_pts, test_pts, n_total=100000, max_cycles=2000, epochs=1500, log=None):
+def experiment(train_pts, test_pts, n_total=100000, max_cycles=2000, epochs=1500, reference=False, log=None):
     """Trains on the converged profiles of cold runs at train_pts, then runs
-    every test point cold and warm in one batch until both converge.  Returns a
-    dict of per-point cycles and profile errors (warm against cold)."""
+    every test point cold and warm (and with reference=True cold again with other
+    random streams) in one batch until all converge.  Returns a dict of
+    per-point cycles and profile errors (against the first cold run)."""
     import time
     import torch
     procs = I.make_processes()
@@ -250,6 +251,7 @@ def experiment(train_pts, test_pts, n_total=100000, max_cycles=2000, epochs=1500
     t0 = time.perf_counter()
     train = make_members(train_pts, procs, stream, n_total=n_total, seed0=7000)
     conv_tr, prof_tr, _ = run_batch(train, max_cycles, log=log)
+    push_data = sum(int(g.counters()[B.C_PUSH:B.C_PUSH + 3].sum()) for g in train)
     for g in train:
         g.close()
     t_data = time.perf_counter() - t0
@@ -261,19 +263,28 @@ def experiment(train_pts, test_pts, n_total=100000, max_cycles=2000, epochs=1500
     warm = [predict(net, std, U, p) for U, p in test_pts]
     cold_m = make_members(test_pts, procs, stream, n_total=n_total, seed0=9000)
     warm_m = make_members(test_pts, procs, stream, n_total=n_total, seed0=9000, warm=warm)
+    # a second cold run with other random streams: how far two plain runs that
+    # both pass the convergence test lie apart
+    ref_m = make_members(test_pts, procs, stream, n_total=n_total, seed0=9500) if reference else []
     t0 = time.perf_counter()
-    conv, prof, cycles = run_batch(cold_m + warm_m, max_cycles, log=log)
+    conv, prof, cycles = run_batch(cold_m + warm_m + ref_m, max_cycles, log=log)
     t_eval = time.perf_counter() - t0
     n = len(test_pts)
     rows = []
     for j, (U, p) in enumerate(test_pts):
         (dc, ec), (dw, ew) = prof[j], prof[n + j]
-        rows.append({"U": U, "p": p, "cold_cycles": conv[j], "warm_cycles": conv[n + j],
-                     "density_error": [profile_error(dw[s], dc[s]) for s in range(3)],
-                     "energy_error": [profile_error(ew[s], ec[s]) for s in range(3)],
-                     "predicted_density_error": [profile_error(warm[j][0][s], dc[s]) for s in range(3)]})
-    for g in cold_m + warm_m:
+        row = {"U": U, "p": p, "cold_cycles": conv[j], "warm_cycles": conv[n + j],
+               "density_error": [profile_error(dw[s], dc[s]) for s in range(3)],
+               "energy_error": [profile_error(ew[s], ec[s]) for s in range(3)],
+               "predicted_density_error": [profile_error(warm[j][0][s], dc[s]) for s in range(3)]}
+        if reference:
+            dr = prof[2 * n + j][0]
+            row["reference_cycles"] = conv[2 * n + j]
+            row["reference_density_error"] = [profile_error(dr[s], dc[s]) for s in range(3)]
+        rows.append(row)
+    push_eval = sum(int(g.counters()[B.C_PUSH:B.C_PUSH + 3].sum()) for g in cold_m + warm_m + ref_m)
+    for g in cold_m + warm_m + ref_m:
         g.close()
     return {"train_points": len(train_pts), "train_converged": [c for c in conv_tr], "loss": hist,
             "rows": rows, "seconds": {"data": t_data, "train": t_train, "eval": t_eval}, "eval_cycles": cycles,
-            "net": net, "std": std}
+            "pushes": {"data": push_data, "eval": push_eval}, "net": net, "std": std}

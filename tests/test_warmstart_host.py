@@ -1,0 +1,65 @@
+"""Host logic of the warm-start pipeline (no GPU): features, target mapping,
+profiles from cycle sums, and the convergence test."""
+import math
+import types
+
+import numpy as np
+
+from paper_0705_0497_amd import warmstart as W
+
+
+def test_features_scale_inputs():
+    f = W.features(300.0, 5.0)
+    assert f.shape == (W.NPTS, 3) and f.dtype == np.float32
+    assert np.allclose(f[:, 0], 0.5) and np.allclose(f[:, 1], -1.0)
+    assert f[0, 2] == 0.0 and f[-1, 2] == 1.0
+    assert np.allclose(W.features(600.0, 100.0)[:, :2], 1.0)
+    assert abs(W.features(100.0, math.sqrt(500.0))[0, 1]) < 1e-6          # geometric middle of [5, 100]
+
+
+def test_targets_round_trip_and_species_order():
+    rng = np.random.default_rng(0)
+    dens = 10 ** rng.uniform(12, 16, size=(3, W.NPTS))
+    mean = rng.uniform(0.03, 5.0, size=(3, W.NPTS))
+    T = W.to_targets(dens, mean)
+    assert np.allclose(T[:, 0], np.log(dens[0])) and np.allclose(T[:, 1], np.log(dens[2]))   # e, O-, O2+
+    assert np.allclose(T[:, 5], mean[1])
+    d2, m2 = W.from_targets(T)
+    assert np.allclose(d2, dens, rtol=1e-12) and np.allclose(m2, mean)
+    std = W.Standardizer.fit(T)
+    assert np.allclose(std.inv(std.fwd(T)), T)
+
+
+def test_profiles_from_cycle_sums():
+    d = W.family(200.0, 20.0, 1)
+    ng = d.ng
+    nacc = 400
+    n0 = 3e14
+    dx = d.L / ng
+    per_node = n0 * dx / d.weight * 2 ** 32                 # fixed-point charge of a uniform density
+    sum_q = np.full((3, ng + 1), per_node * nacc)
+    sum_q[:, [0, -1]] *= 0.5                                # half cells at the electrodes
+    ecnt = np.full((3, ng), 100, np.int64)
+    esum = (ecnt * np.array([[3.0], [0.05], [0.04]]) * 2 ** 20).astype(np.int64)
+    g = types.SimpleNamespace(d=d)
+    dens, mean = W.cycle_profiles(g, {"sum_q": sum_q, "nacc": nacc, "esum": esum, "ecnt": ecnt})
+    assert np.allclose(dens, n0, rtol=1e-12)
+    assert np.allclose(mean, [[3.0], [0.05], [0.04]], rtol=1e-6)
+
+
+def test_convergence_needs_two_consecutive_windows_within_one_percent_over_twenty_cycles():
+    m = W.Monitor()
+    base = np.ones(10)
+    seq = [1.0, 1.5, 1.2, 1.205, 1.21, 1.212, 1.213]        # windows 10, 20, ..., 70 cycles
+    got = [m.add(base * v, 10 * (k + 1)) for k, v in enumerate(seq)]
+    # window 4 vs 2: |1.205 - 1.5| large; window 5 vs 3: 0.8 %; window 6 vs 4: 0.6 % -> converged at 60
+    assert got[:5] == [None] * 5 and got[5] == 60 and got[6] == 60
+    m2 = W.Monitor()
+    assert [m2.add(base, 10 * (k + 1)) for k in range(4)] == [None, None, None, 40]   # earliest possible
+
+
+def test_sample_points_cover_the_domain():
+    pts = W.sample_points(200, 3)
+    U = np.array([a for a, _ in pts])
+    p = np.array([b for _, b in pts])
+    assert U.min() >= 150 and U.max() <= 350 and p.min() >= 15 and p.max() <= 40
