@@ -119,6 +119,7 @@ struct Sim {
   long long *events;
   int64_t event_cap;
   int32_t pair_rounds;
+  int32_t rq_cap;                  // electron candidate records kept in LDS per pass
 };
 
 // device state of a batch of discharges advanced together

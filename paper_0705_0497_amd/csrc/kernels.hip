@@ -390,6 +390,12 @@ struct PushShared {
   float *tab;              // [np][ntab]
   float *ttot;             // [ntab] sum_p scale_p sigma_p (electrons: early null test)
   unsigned short *queue;   // [GROUP BS] candidate slots relative to the pass base
+  // electrons: state of the first rq_cap candidates of a pass, written by their
+  // owning thread from registers so that the block does not re-read it from HBM
+  int32_t *rw;
+  float *roff, *rvx, *rvy, *rvz;
+  uint32_t *rid;
+  unsigned short *rslot;
 };
 
 __device__ __forceinline__ size_t align_up(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -634,7 +640,7 @@ __device__ __forceinline__ int64_t push_chunk(int64_t N, int grid) {
 #endif
 // block-level LDS state of a push run besides the dynamic part
 struct PushLds {
-  int qn[2];
+  int qn[16];              // queued candidates of each wave in the current pass
   BlockCounts bc;
   WallHist wall;
 };
@@ -656,7 +662,15 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
   sh.N = (float *)(smem + o); if (S_ == 2) o = align_up(o + sizeof(float) * nn);
   sh.tab = (float *)(smem + o); o = align_up(o + sizeof(float) * np * S.ntab);
   sh.ttot = (float *)(smem + o); if (S_ == 0) o = align_up(o + sizeof(float) * S.ntab);
-  sh.queue = (unsigned short *)(smem + o);
+  sh.queue = (unsigned short *)(smem + o); o = align_up(o + sizeof(unsigned short) * GROUP * BS);
+  const int rq_cap = S_ == 0 ? S.rq_cap : 0;
+  sh.rw = (int32_t *)(smem + o); o += 4 * (size_t)rq_cap;
+  sh.roff = (float *)(smem + o); o += 4 * (size_t)rq_cap;
+  sh.rvx = (float *)(smem + o); o += 4 * (size_t)rq_cap;
+  sh.rvy = (float *)(smem + o); o += 4 * (size_t)rq_cap;
+  sh.rvz = (float *)(smem + o); o += 4 * (size_t)rq_cap;
+  sh.rid = (uint32_t *)(smem + o); o += 4 * (size_t)rq_cap;
+  sh.rslot = (unsigned short *)(smem + o);
   for (int j = threadIdx.x; j < 2 * NBIN; j += BS) wall.iedf[j / NBIN][j % NBIN] = 0u;
   for (int j = threadIdx.x; j < nn; j += BS) {
     sh.Q[j] = 0ull;
@@ -668,7 +682,7 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
   if (S_ == 0)
     for (int j = threadIdx.x; j < S.ntab; j += BS) sh.ttot[j] = S.ttot_e[j];
   for (int k = threadIdx.x; k < NCOUNT; k += BS) bc.c[k] = 0u;
-  if (threadIdx.x == 0) { qn[0] = 0; qn[1] = 0; }
+  if (threadIdx.x < 16) qn[threadIdx.x] = 0;
   float inv_numax = 0.0f;
   double pnull = 0.0;
   if (S_ == 1) pnull = S.pnull_pos;
@@ -679,12 +693,20 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
   const float qmdt = S.qmdt[S_], dtdx = S.dtdx[S_];
   const bool nocoll = (S.flags & F_NO_COLL) != 0;
   const int lane = threadIdx.x & 63;
+  // Electrons: each wave queues the collision candidates of its own GROUP * 64 slots
+  // of a pass (their state as LDS records while the wave's share lasts) and works
+  // them off itself, so the waves of a block never wait for each other inside a run.
+  // Ions: one queue per block, worked off by all its lanes between two barriers.
+  const int wv = threadIdx.x >> 6;
+  int *wcnt = &qn[wv];
+  unsigned short *wq = sh.queue + wv * GROUP * 64;
+  const int rqw = rq_cap / (BS / 64), r0 = wv * rqw;
   ThreadCounts tc;
   DepRun run;
   int par = 0;
   for (int64_t base = begin; base < end; base += (int64_t)GROUP * BS, par ^= 1) {
     const int64_t i0 = base + (int64_t)GROUP * threadIdx.x;
-    unsigned int cmask = 0u;
+    unsigned int cmask = 0u;               // ion candidates of this thread (electrons queue directly)
     if (i0 < end) {
       const int nv = (int)min((int64_t)GROUP, end - i0);
       int32_t w[GROUP];
@@ -760,7 +782,16 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
               if (en.clamped) count_lanes(bc, C_CLAMP);
               const TabPos tp = tab_pos(S, en.ec);
               if (unif(c.y) < electron_bound(sh, tp, en.g) * 1.000001f) {
-                cmask |= 1u << k;                      // may collide: channel chosen by the block
+                // may collide: the channel is chosen by the block after the pass
+                const int e = atomicAdd(wcnt, 1);
+                const unsigned short slot = (unsigned short)(i0 - base + k);
+                if (e < rqw) {
+                  const int r = r0 + e;
+                  sh.rw[r] = w[k]; sh.roff[r] = no; sh.rvx[r] = v; sh.rvy[r] = vy[k]; sh.rvz[r] = vz[k];
+                  sh.rid[r] = id[k]; sh.rslot[r] = slot;
+                } else {
+                  wq[e - rqw] = slot;
+                }
               } else {                                 // null collision
                 run.add(sh.Q, nc, no);
                 ++tc.nul;
@@ -787,35 +818,60 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
         for (int k = 0; k < nv; ++k) { P.w[i0 + k] = w[k]; P.off[i0 + k] = off[k]; P.vx[i0 + k] = vx[k]; }
       }
     }
-    // queue the candidates: one LDS atomic per wave
-    const int mine = __popc(cmask);
-    int incl = wave_incl_scan(mine);
-    int wbase = 0;
-    if (lane == 63 && incl > 0) wbase = atomicAdd(&qn[par], incl);
-    wbase = __shfl(wbase, 63, 64);
-    int q = wbase + incl - mine;
-    for (unsigned int m = cmask; m; m &= m - 1) sh.queue[q++] = (unsigned short)(i0 - base + __ffs(m) - 1);
-    __syncthreads();
-    const int nq = qn[par];
-    if (threadIdx.x == 0) qn[par ^ 1] = 0;     // counter of the next pass, unused since the last barrier
-    for (int k = threadIdx.x; k < nq; k += CAND_ILP * BS) {
-      // gathers of up to CAND_ILP candidates in flight together
-      Cand c[CAND_ILP];
-      bool h[CAND_ILP];
-#pragma unroll
-      for (int u = 0; u < CAND_ILP; ++u) {
-        h[u] = k + u * BS < nq;
-        if (h[u]) c[u] = load_cand(P, base + sh.queue[k + u * BS]);
+    if (S_ == 0) {
+      // the wave's queue is complete: its LDS and global writes are visible to its lanes
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      const int nq = *wcnt;
+      for (int e = lane; e < nq; e += 64) {
+        Cand c;
+        if (e < rqw) {
+          const int r = r0 + e;
+          c.i = base + sh.rslot[r]; c.w = sh.rw[r]; c.id = sh.rid[r]; c.off = sh.roff[r];
+          c.vx = sh.rvx[r]; c.vy = sh.rvy[r]; c.vz = sh.rvz[r];
+        } else {
+          c = load_cand(P, base + wq[e - rqw]);
+        }
+        collide_electron(S, step, c, sh, bc, tc);
       }
+      // every lane has read the count and its entries: reset for the next pass
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      if (lane == 0) *wcnt = 0;
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } else {
+      // queue the candidates: one LDS atomic per wave
+      const int mine = __popc(cmask);
+      const int incl = wave_incl_scan(mine);
+      int wbase = 0;
+      if (lane == 63 && incl > 0) wbase = atomicAdd(&qn[par], incl);
+      wbase = __shfl(wbase, 63, 64);
+      int q = wbase + incl - mine;
+      for (unsigned int m = cmask; m; m &= m - 1) sh.queue[q++] = (unsigned short)(i0 - base + __ffs(m) - 1);
+      __syncthreads();
+      const int nq = qn[par];
+      if (threadIdx.x == 0) qn[par ^ 1] = 0;   // counter of the next pass, unused since the last barrier
+      for (int k = threadIdx.x; k < nq; k += CAND_ILP * BS) {
+        // gathers of up to CAND_ILP candidates in flight together
+        Cand c[CAND_ILP];
+        bool h[CAND_ILP];
 #pragma unroll
-      for (int u = 0; u < CAND_ILP; ++u) {
-        if (!h[u]) continue;
-        if (S_ == 0) collide_electron(S, step, c[u], sh, bc, tc);
-        else collide_ion<S_>(S, step, c[u], sh, bc, tc, inv_numax);
+        for (int u = 0; u < CAND_ILP; ++u) {
+          h[u] = k + u * BS < nq;
+          if (h[u]) c[u] = load_cand(P, base + sh.queue[k + u * BS]);
+        }
+#pragma unroll
+        for (int u = 0; u < CAND_ILP; ++u)
+          if (h[u]) collide_ion<S_>(S, step, c[u], sh, bc, tc, inv_numax);
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
+  __syncthreads();
   run.flush(sh.Q);
   atomicAdd(&bc.c[C_PUSH + S_], tc.push);
   if (tc.cand) atomicAdd(&bc.c[C_CAND + S_], tc.cand);
@@ -1445,7 +1501,8 @@ size_t push_lds_bytes(const Sim &S, int s, int bs) {
   if (s == 2) o = (o + 4 * nn + 15) & ~(size_t)15;
   o = (o + 4 * (size_t)S.nproc_sp[s] * S.ntab + 15) & ~(size_t)15;
   if (s == 0) o = (o + 4 * (size_t)S.ntab + 15) & ~(size_t)15;
-  o += sizeof(unsigned short) * GROUP * (size_t)bs;
+  o = (o + sizeof(unsigned short) * GROUP * (size_t)bs + 15) & ~(size_t)15;
+  if (s == 0) o += 26 * (size_t)S.rq_cap;          // candidate records: 6 words + a 16-bit slot
   return o;
 }
 

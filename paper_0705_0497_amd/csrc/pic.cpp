@@ -409,14 +409,23 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
   S.ttot_e = (const float *)(ws + L.ttot);
   S.blkcnt = (long long *)(ws + L.blkcnt);
 
-  // launch shapes
+  // launch shapes.  The electron push keeps the state of its first candidates of
+  // each pass in LDS; give it what the resident blocks (at most 1024 threads per
+  // CU at the push kernels' 128 registers) leave free, beside 3 KB of static LDS.
+  const size_t lds_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : prop.sharedMemPerBlock;
+  {
+    S.rq_cap = 0;
+    const size_t base = push_lds_bytes(S, 0, h->block) + 3072;
+    const size_t per_cu = std::max<size_t>(1, std::min<size_t>(lds_cu / base, 1024 / h->block));
+    const size_t budget = std::min<size_t>(lds_cu / per_cu, prop.sharedMemPerBlock);
+    S.rq_cap = budget > base ? (int)(std::min<size_t>(1024, (budget - base) / 26) & ~(size_t)3) : 0;
+  }
   const size_t lds_need = max_push_lds(S, h->block);
   if (lds_need > prop.sharedMemPerBlock) {
     g_query_error = "grid too large for the LDS of one block (" + std::to_string(lds_need) + " bytes)";
     delete h;
     return PIC_EINVAL;
   }
-  const size_t lds_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : prop.sharedMemPerBlock;
   for (int s = 0; s < NSP; ++s) {
     const size_t lds = push_lds_bytes(S, s, h->block);
     int per_cu = (int)std::min<size_t>(2048 / h->block, std::max<size_t>(1, lds_cu / lds));
