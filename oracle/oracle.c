@@ -52,6 +52,14 @@ struct orc_sim {
   int32_t logon;
   int64_t nev, evcap, *ev;
   int64_t born_start[ORC_NSP];
+  /* current density at the driven electrode, per phase of the rf cycle */
+  double *jsum;                /* steps_per_cycle sums [A/m^2] */
+  int64_t *jcnt;
+  double psum;                 /* sum of U j over the samples [W/m^2] */
+  int64_t pn;
+  int32_t jvalid;              /* e0_prev, u_prev, abs0_prev hold the previous field solve */
+  double e0_prev, u_prev;
+  int64_t abs0_prev[ORC_NSP];
 };
 
 /* ------------------------------------------------------------------ */
@@ -238,6 +246,8 @@ orc_sim *orc_create(const orc_config *cfg, const orc_species *sp, int32_t nproc,
   S->edf = calloc((size_t)ORC_NSP * ORC_NBIN, sizeof(int64_t));
   S->iedf = calloc((size_t)ORC_NSP * 2 * ORC_NBIN, sizeof(int64_t));
   S->kcell = calloc(cfg->ng, sizeof(int64_t));
+  S->jsum = calloc(cfg->steps_per_cycle, sizeof(double));
+  S->jcnt = calloc(cfg->steps_per_cycle, sizeof(int64_t));
   S->numax[ORC_E] = nu_bound(S, ORC_E, NULL);
   S->numax[ORC_POS] = nu_bound(S, ORC_POS, NULL);
   S->numax[ORC_NEG] = 0.0;   /* set at each ion step from the O2+ density */
@@ -253,6 +263,7 @@ void orc_destroy(orc_sim *S) {
   }
   free(S->sigma); free(S->Q); free(S->phi); free(S->E); free(S->sumQ); free(S->sumphi);
   free(S->esum); free(S->ecnt); free(S->edf); free(S->iedf); free(S->kcell); free(S->ev);
+  free(S->jsum); free(S->jcnt);
   free(S);
 }
 
@@ -358,6 +369,7 @@ int orc_load_profile(orc_sim *S, int32_t n_pts, const double *xs, const double *
 int orc_set_particles(orc_sim *S, int32_t s, int64_t n, const int32_t *cell, const float *off,
                       const float *vx, const float *vy, const float *vz, const uint32_t *id,
                       const int32_t *cdw, uint32_t next_id) {
+  S->jvalid = 0;
   orc_store *a = &S->st[s];
   a->n = 0;
   store_reserve(a, n);
@@ -375,6 +387,7 @@ int orc_set_particles(orc_sim *S, int32_t s, int64_t n, const int32_t *cell, con
 int orc_set_particles64(orc_sim *S, int32_t s, int64_t n, const double *xi, const double *vx,
                         const double *vy, const double *vz, const uint32_t *id, const int32_t *cdw,
                         uint32_t next_id) {
+  S->jvalid = 0;
   orc_store *a = &S->st[s];
   a->n = 0;
   store_reserve(a, n);
@@ -407,7 +420,7 @@ void orc_get_particles(const orc_sim *S, int32_t s, double *xi, double *vx, doub
   }
 }
 
-void orc_set_step(orc_sim *S, int64_t step) { S->step = step; }
+void orc_set_step(orc_sim *S, int64_t step) { S->step = step; S->jvalid = 0; }
 int64_t orc_get_step(const orc_sim *S) { return S->step; }
 
 /* ------------------------------------------------------------------ */
@@ -492,7 +505,33 @@ static void field(orc_sim *S) {
   free(rho);
 }
 
+/* Section 3: current density through the discharge and power <U j> A.  Between two
+   field solves (steps n-1 and n) the current density at x = 0 in +x is the
+   displacement part eps0 (E_0^n - E_0^(n-1)) / dt plus the conduction part of the
+   charge absorbed at x = 0 in between (moving in -x): -e w sum_s q_s dN_s / dt.
+   It is summed at phase (n-1) mod steps_per_cycle; the power sums
+   (U^(n-1) + U^n) / 2 times it. */
+static void current_sample(orc_sim *S) {
+  double e0 = S->E[0];
+  double u = S->c.U * sin(TWO_PI * S->c.f * ((double)S->step * S->dt));
+  if (S->jvalid) {
+    double dq = 0.0;
+    for (int s = 0; s < ORC_NSP; ++s) dq += S->sp[s].charge * (double)(S->cnt[ORC_C_ABS0 + s] - S->abs0_prev[s]);
+    double j = EPS0 * (e0 - S->e0_prev) / S->dt - Q_E * S->c.weight * dq / S->dt;
+    int64_t ph = (S->step - 1) % S->c.steps_per_cycle;
+    S->jsum[ph] += j;
+    S->jcnt[ph] += 1;
+    S->psum += 0.5 * (S->u_prev + u) * j;
+    S->pn += 1;
+  }
+  S->e0_prev = e0;
+  S->u_prev = u;
+  for (int s = 0; s < ORC_NSP; ++s) S->abs0_prev[s] = S->cnt[ORC_C_ABS0 + s];
+  S->jvalid = 1;
+}
+
 void orc_prepare(orc_sim *S, int32_t shift) {
+  S->jvalid = 0;
   for (int s = 0; s < ORC_NSP; ++s) deposit_species(S, s);
   if (!shift) return;
   field(S);
@@ -798,6 +837,7 @@ static void one_step(orc_sim *S) {
   int ng = S->c.ng, nn = ng + 1;
   /* 1. field from the charge left by the previous step; moments of that state */
   field(S);
+  current_sample(S);
   for (int k = 0; k < ORC_NSP * nn; ++k) S->sumQ[k] += (double)S->Q[k];
   for (int j = 0; j < nn; ++j) S->sumphi[j] += S->phi[j];
   S->nacc++;
@@ -869,6 +909,17 @@ void orc_reset_moments(orc_sim *S) {
   memset(S->iedf, 0, sizeof(int64_t) * ORC_NSP * 2 * ORC_NBIN);
   S->nacc = 0;
   S->ndiag = 0;
+  memset(S->jsum, 0, sizeof(double) * S->c.steps_per_cycle);
+  memset(S->jcnt, 0, sizeof(int64_t) * S->c.steps_per_cycle);
+  S->psum = 0.0;
+  S->pn = 0;
+}
+
+void orc_get_current(const orc_sim *S, double *jsum, int64_t *jcnt, double *psum, int64_t *pn) {
+  if (jsum) memcpy(jsum, S->jsum, sizeof(double) * S->c.steps_per_cycle);
+  if (jcnt) memcpy(jcnt, S->jcnt, sizeof(int64_t) * S->c.steps_per_cycle);
+  if (psum) *psum = S->psum;
+  if (pn) *pn = S->pn;
 }
 
 int64_t orc_get_moments(const orc_sim *S, double *sumQ, double *sumphi, int64_t *esum, int64_t *ecnt,

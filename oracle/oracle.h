@@ -132,6 +132,11 @@ void orc_reset_moments(orc_sim *S);
 int64_t orc_get_moments(const orc_sim *S, double *sumQ, double *sumphi, int64_t *esum, int64_t *ecnt,
                         int64_t *edf, int64_t *iedf, int64_t *ndiag);
 
+/* current density at the driven electrode (section 3): per phase of the rf cycle
+   the sums of j [A/m^2] and their counts, and the sum of U j [W/m^2] over the
+   samples; cleared with the other moments */
+void orc_get_current(const orc_sim *S, double *jsum, int64_t *jcnt, double *psum, int64_t *pn);
+
 /* event log: records of 6 int64 {step, species, id, code, band, aux};
    code >= 0 process index, -1 null, -2 capped redraw, -3 absorbed */
 void orc_log_events(orc_sim *S, int32_t on);

@@ -72,6 +72,7 @@ def lib():
         L.orc_load_uniform.argtypes = [vp]
         L.orc_load_profile.argtypes = [vp, i32, vp, vp, vp]
         L.orc_load_profile.restype = i32
+        L.orc_get_current.argtypes = [vp, vp, vp, vp, vp]
         L.orc_set_particles.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, vp, u32]
         L.orc_set_particles64.argtypes = [vp, i32, i64, vp, vp, vp, vp, vp, vp, u32]
         L.orc_count.restype = i64
@@ -277,6 +278,17 @@ class Oracle:
         nacc = lib().orc_get_moments(self.h, _p(sumQ), _p(sumphi), _p(esum), _p(ecnt), _p(edf), _p(iedf), _p(nd))
         return dict(nacc=nacc, sumQ=sumQ, sumphi=sumphi, esum=esum, ecnt=ecnt, edf=edf, iedf=iedf,
                     ndiag=int(nd[0]))
+
+    def current(self):
+        """Current density at the driven electrode: per-phase sums and counts over
+        the rf cycle, and the sum of U j over the samples with its count."""
+        spc = self.d.steps_per_cycle
+        js = np.zeros(spc)
+        jc = np.zeros(spc, dtype=np.int64)
+        ps = np.zeros(1)
+        pn = np.zeros(1, dtype=np.int64)
+        lib().orc_get_current(self.h, _p(js), _p(jc), _p(ps), _p(pn))
+        return {"jsum": js, "jcnt": jc, "psum": float(ps[0]), "pn": int(pn[0])}
 
     def log_events(self, on=True):
         lib().orc_log_events(self.h, 1 if on else 0)

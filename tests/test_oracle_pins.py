@@ -597,3 +597,90 @@ def test_profile_loading_rejects_invalid_profiles():
         with pytest.raises(ValueError):
             o.load_profile(*bad)
     o.load_profile(*good)
+
+
+# ---------------------------------------------------------------- current density and power (section 3)
+def test_current_of_the_empty_gap_is_the_capacitor_current_and_draws_no_power():
+    d = I.config(1)
+    o = po.Oracle(d, species(), I.make_processes())
+    for s in range(3):
+        empty(o, s)
+    o.set_step(0)
+    o.prepare(True)
+    spc = d.steps_per_cycle
+    o.step(spc + 1)
+    c = o.current()
+    assert np.all(c["jcnt"] == 1)
+    dt = 1.0 / (d.f * spc)
+    t = np.arange(spc + 1) * dt
+    u = d.U * np.sin(2 * np.pi * d.f * t)
+    expect = EPS0 * (u[1:] - u[:-1]) / d.L / dt                 # vacuum: E = U(t) / L everywhere
+    np.testing.assert_allclose(c["jsum"], expect, rtol=1e-9, atol=1e-12 * np.max(np.abs(expect)))
+    # a capacitor takes back over the cycle what it receives: the power sum telescopes to zero
+    scale = EPS0 * d.U ** 2 / d.L / dt
+    assert abs(c["psum"]) < 1e-9 * scale and c["pn"] == spc
+
+
+def test_total_current_is_the_same_at_both_electrodes():
+    # Gauss's law over the gap, E_N - E_0 = Q_gap / eps0 with the half-cell boundary fields,
+    # and charge-neutral reactions: the current at x = L, from E_N and the tallies at x = L,
+    # must equal the one recorded at x = 0 in every step
+    d = I.config(1, n_total=6000, U=300.0)
+    procs = I.make_processes()
+    o = po.Oracle(d, d.species(), procs)
+    o.load_uniform()
+    o.prepare(True)
+    dt = 1.0 / (d.f * d.steps_per_cycle)
+    qs = np.array([-1.0, 1.0, -1.0])
+    ew = QE * d.weight
+    o.step(1)
+    _, E = o.field()                      # field solved at the start of the last step
+    cnt_before = o.counters()             # tallies before the last step's pushes are in cnt_prev
+    cnt_prev = cnt_before.copy()
+    o.step(1)
+    _, E2 = o.field()
+    cnt = o.counters()
+    # step n: field E^n, then pushes; the sample of step n pairs E^n - E^(n-1) with what
+    # was absorbed by the pushes of step n-1 (between the two field solves)
+    j0_prev = o.current()["jsum"].copy()
+    E, cnt_prev = E2, cnt_before
+    checked = 0
+    for k in range(60):
+        o.step(1)
+        _, E2 = o.field()
+        cnt2 = o.counters()
+        dL = cnt[po.C_ABSL:po.C_ABSL + 3] - cnt_prev[po.C_ABSL:po.C_ABSL + 3]
+        d0 = cnt[po.C_ABS0:po.C_ABS0 + 3] - cnt_prev[po.C_ABS0:po.C_ABS0 + 3]
+        jL = EPS0 * (E2[-1] - E[-1]) / dt + ew * float(np.dot(qs, dL)) / dt
+        j0 = EPS0 * (E2[0] - E[0]) / dt - ew * float(np.dot(qs, d0)) / dt
+        rec = o.current()["jsum"]
+        got = float((rec - j0_prev)[(o.step_index - 2) % d.steps_per_cycle])
+        j0_prev = rec.copy()
+        scale = EPS0 * np.max(np.abs(E2)) / dt
+        assert abs(got - j0) <= 1e-9 * scale
+        assert abs(jL - j0) <= 1e-8 * scale, (k, j0, jL)
+        checked += bool(d0.any())
+        E, cnt_prev, cnt = E2, cnt, cnt2
+    assert checked > 5                                                  # steps with absorption at x = 0
+
+
+def test_conduction_current_of_a_beam_into_the_driven_electrode():
+    d = I.config(1, ng=64)
+    o = po.Oracle(d, species(), I.make_processes(), flags=po.F_EXT_FIELD | po.F_NO_COLL)
+    dt = 1.0 / (d.f * d.steps_per_cycle)
+    dx = d.L / d.ng
+    v = 0.37 * dx / dt                                                  # 0.37 cells per step towards x = 0
+    xi = np.linspace(0.05, 6.0, 200)                                    # cell coordinates
+    put(o, 0, xi, -v * np.ones(200))
+    empty(o, 1)
+    empty(o, 2)
+    o.set_step(0)
+    o.prepare(False)
+    o.step(25)
+    c = o.current()
+    # electron k leaves at the first step m with xi_k - m * 0.37 < 0; its charge -e crosses x = 0 in -x
+    m = np.floor(xi / 0.37).astype(int) + 1
+    m[xi - (m - 1) * 0.37 < 0] -= 1
+    per_step = np.bincount(m, minlength=40)
+    expect = QE * d.weight * per_step[1:25] / dt                         # samples of steps 1..24
+    np.testing.assert_allclose(c["jsum"][:24], expect, rtol=1e-12, atol=0)
