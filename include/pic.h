@@ -140,6 +140,16 @@ typedef struct pic_moments_out {
   int64_t *iedf;           /* [3][2][PIC_NBIN] energies of particles absorbed at x=0 / x=L */
   int64_t nacc;            /* steps accumulated in sum_q / sum_phi */
   int64_t ndiag;           /* diagnostic samples in esum / ecnt / edf */
+  /* Section 3, current density through the discharge and power <U j> A: between
+     the field solves of steps n-1 and n the current density at x = 0 in +x is
+     eps0 (E_0^n - E_0^(n-1)) / dt (displacement; E_0 the Gauss-law node field)
+     plus -e w sum_s q_s dN_s / dt for the dN_s particles absorbed at x = 0 in
+     between; it is summed at phase (n-1) mod steps_per_cycle.  Ions absorbed in
+     an ion step appear in that step (the ions move every ksub steps). */
+  double *current;         /* [steps_per_cycle] sums of j [A/m^2] per phase */
+  int64_t *current_n;      /* [steps_per_cycle] samples per phase */
+  double power_sum;        /* sum over the samples of (U^(n-1) + U^n) / 2 j [W/m^2] */
+  int64_t power_n;         /* samples in power_sum; power per electrode area = power_sum / power_n */
 } pic_moments_out;
 
 typedef struct pic_handle pic_handle;

@@ -68,7 +68,9 @@ class pic_process(C.Structure):
 
 class pic_moments_out(C.Structure):
     _fields_ = [("sum_q", C.c_void_p), ("sum_phi", C.c_void_p), ("esum", C.c_void_p), ("ecnt", C.c_void_p),
-                ("edf", C.c_void_p), ("iedf", C.c_void_p), ("nacc", C.c_int64), ("ndiag", C.c_int64)]
+                ("edf", C.c_void_p), ("iedf", C.c_void_p), ("nacc", C.c_int64), ("ndiag", C.c_int64),
+                ("current", C.c_void_p), ("current_n", C.c_void_p), ("power_sum", C.c_double),
+                ("power_n", C.c_int64)]
 
 
 class pic_batch_config(C.Structure):
@@ -279,13 +281,16 @@ def pic_sync(h):
     _check(lib().pic_sync(h), h)
 
 
-def pic_moments(h, ng, reset=False):
+def pic_moments(h, ng, reset=False, steps_per_cycle=1):
     m = {"sum_q": np.zeros((3, ng + 1)), "sum_phi": np.zeros(ng + 1), "esum": np.zeros((3, ng), np.int64),
          "ecnt": np.zeros((3, ng), np.int64), "edf": np.zeros((3, NBIN), np.int64),
-         "iedf": np.zeros((3, 2, NBIN), np.int64)}
-    o = pic_moments_out(*[_ptr(m[k]) for k in ("sum_q", "sum_phi", "esum", "ecnt", "edf", "iedf")], 0, 0)
+         "iedf": np.zeros((3, 2, NBIN), np.int64), "current": np.zeros(steps_per_cycle),
+         "current_n": np.zeros(steps_per_cycle, np.int64)}
+    o = pic_moments_out(*[_ptr(m[k]) for k in ("sum_q", "sum_phi", "esum", "ecnt", "edf", "iedf")], 0, 0,
+                        _ptr(m["current"]), _ptr(m["current_n"]), 0.0, 0)
     _check(lib().pic_moments(h, C.byref(o), 1 if reset else 0), h)
     m["nacc"], m["ndiag"] = o.nacc, o.ndiag
+    m["power_sum"], m["power_n"] = o.power_sum, o.power_n
     return m
 
 
@@ -396,7 +401,7 @@ class Discharge:
         pic_sync(self.h)
 
     def moments(self, reset=False):
-        return pic_moments(self.h, self.ng, reset)
+        return pic_moments(self.h, self.ng, reset, self.d.steps_per_cycle)
 
     def hist(self):
         return pic_get_hist(self.h, self.ng)

@@ -44,6 +44,11 @@ struct Scalars {
   uint32_t ticket;                 // last-block-done counter
   int32_t pad;
   unsigned long long nsort[NSP];   // slots seen by the running sort
+  // current density at the driven electrode: state of the previous field solve
+  double e0_prev, u_prev;
+  unsigned long long abs0_prev[NSP];
+  int32_t jvalid;
+  int32_t pad2;
 };
 
 struct Particles {
@@ -120,6 +125,10 @@ struct Sim {
   int64_t event_cap;
   int32_t pair_rounds;
   int32_t rq_cap;                  // electron candidate records kept in LDS per pass
+  int32_t spc;                     // steps per rf cycle
+  double *jsum;                    // [spc] current density sums per phase [A/m^2]
+  unsigned long long *jcnt;        // [spc] samples per phase
+  double *jpow;                    // [2] sum of U j [W/m^2], number of samples (as a double)
 };
 
 // device state of a batch of discharges advanced together

@@ -244,6 +244,7 @@ __device__ void field_block(const Sim &S, int64_t step, int mode) {
   double jtot;
   const double jbase = block_exclusive_scan<BS, double>(jloc, sJ, jtot);
   double phiv[FIELD_PER];
+  double e0v = S.e_ext0 - 0.5 * S.e_ext1 * S.L;    // node-0 field (external-field mode)
   if (!(S.flags & F_EXT_FIELD)) {
     const double c = S.qcharge;            // e w 2^-32: charge per unit area per fixed-point unit
     const double phi0 = S.U * sin(2.0 * M_PI * S.f * ((double)step * S.dt));
@@ -266,11 +267,38 @@ __device__ void field_block(const Sim &S, int64_t step, int mode) {
       S.phi[j] = phi;
       S.E[j] = (float)e;
       phiv[u] = phi;
+      if (j == 0) e0v = e;
       if (j < ng) jrun += (double)run;
     }
   } else {
 #pragma unroll
     for (int u = 0; u < FIELD_PER; ++u) phiv[u] = 0.0;
+  }
+  // Section 3: current density at x = 0 in +x between this solve and the previous one,
+  // eps0 dE_0/dt plus the charge absorbed at x = 0 in between, summed per rf phase
+  if (t == 0) {
+    Scalars *sc = S.sc;
+    const double u = S.U * sin(2.0 * M_PI * S.f * ((double)step * S.dt));
+    if (mode == 0 && sc->jvalid) {
+      double dq = 0.0;
+      for (int s = 0; s < NSP; ++s)
+        dq += (double)S.charge[s] * (double)(long long)(sc->cnt[C_ABS0 + s] - sc->abs0_prev[s]);
+      const double ew = S.qcharge * 4294967296.0;     // e w
+      const double jx = S.eps0 * (e0v - sc->e0_prev) / S.dt - ew * dq / S.dt;
+      const int ph = (int)((step - 1) % S.spc);
+      S.jsum[ph] += jx;
+      S.jcnt[ph] += 1ull;
+      S.jpow[0] += 0.5 * (sc->u_prev + u) * jx;
+      S.jpow[1] += 1.0;
+    }
+    if (mode == 0) {
+      sc->e0_prev = e0v;
+      sc->u_prev = u;
+      for (int s = 0; s < NSP; ++s) sc->abs0_prev[s] = sc->cnt[C_ABS0 + s];
+      sc->jvalid = 1;
+    } else {
+      sc->jvalid = 0;
+    }
   }
   if (mode != 0) return;
   // cycle sums of the state this solve saw, then clear what this step rebuilds

@@ -59,7 +59,7 @@ struct Layout {
   size_t part[NSP][2][6];   // two buffers x (w, off, vx, vy, vz, id)
   size_t pkey[NSP], pbkt[NSP], ptmp[NSP], bcnt;
   size_t Q, E, phi, sumQ, sumphi, esum, ecnt, edf, iedf, nacc, kleft, cmin, sortcnt, sortbase, sc, sigma,
-      hbound, events, partials, ttot, blkcnt, prof;
+      hbound, events, partials, ttot, blkcnt, prof, jsum, jcnt, jpow;
   size_t take(size_t bytes) {
     const size_t o = total;
     total += (bytes + 255) & ~(size_t)255;
@@ -101,6 +101,9 @@ Layout make_layout(const pic_config &c, const pic_species *sp, int nproc) {
   L.ttot = L.take(4 * (size_t)c.table_n);
   L.blkcnt = L.take(8 * 4096);
   L.prof = L.take((8 + 4) * NSP * (size_t)c.ng);   // warm-start loading: per-cell cumulative counts, speeds
+  L.jsum = L.take(8 * (size_t)c.steps_per_cycle);   // current density per rf phase
+  L.jcnt = L.take(8 * (size_t)c.steps_per_cycle);
+  L.jpow = L.take(16);
   return L;
 }
 
@@ -408,6 +411,10 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
   S.part = (unsigned long long *)(ws + L.partials);
   S.ttot_e = (const float *)(ws + L.ttot);
   S.blkcnt = (long long *)(ws + L.blkcnt);
+  S.spc = c.steps_per_cycle;
+  S.jsum = (double *)(ws + L.jsum);
+  S.jcnt = (unsigned long long *)(ws + L.jcnt);
+  S.jpow = (double *)(ws + L.jpow);
 
   // launch shapes.  The electron push keeps the state of its first candidates of
   // each pass in LDS; give it what the resident blocks (at most 1024 threads per
@@ -489,6 +496,11 @@ int pic_prepare(pic_handle *h, int32_t shift) {
   if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   Sim &S = h->S;
   const size_t nn = h->cfg.ng + 1;
+  {
+    const int32_t z = 0;                          // the next field solve starts the current series
+    const int r = set_scalar(h, offsetof(Scalars, jvalid), &z, 4);
+    if (r != PIC_OK) return r;
+  }
   HIPCHK(h, hipMemsetAsync(S.Q, 0, 8 * NSP * nn, h->stream));
   for (int s = 0; s < NSP; ++s) HIPCHK(h, launch_deposit(S, s, h->hgrid, h->stream));
   if (shift) {
@@ -642,7 +654,9 @@ int pic_set_particles(pic_handle *h, int32_t s, int64_t n, const int32_t *cell, 
     HIPCHK(h, hipMemcpy(P.id, id, 4 * n, hipMemcpyHostToDevice));
   }
   unsigned long long nn = (unsigned long long)n, z = 0;
-  int r = set_scalar(h, offsetof(Scalars, n) + 8 * s, &nn, 8);
+  const int32_t zi = 0;
+  int r = set_scalar(h, offsetof(Scalars, jvalid), &zi, 4);
+  if (r == PIC_OK) r = set_scalar(h, offsetof(Scalars, n) + 8 * s, &nn, 8);
   if (r == PIC_OK) r = set_scalar(h, offsetof(Scalars, nnew) + 8 * s, &z, 8);
   if (r == PIC_OK) r = set_scalar(h, offsetof(Scalars, next_id) + 4 * s, &next_id, 4);
   return r;
@@ -714,6 +728,13 @@ int pic_get_particles(pic_handle *h, int32_t s, int64_t *n, int32_t *cell, float
 
 int pic_set_step(pic_handle *h, int64_t step) {
   if (!h || step < 0) return PIC_EINVAL;
+  {
+    const int32_t z = 0;
+    if (!h->batch_busy) {
+      const int r = set_scalar(h, offsetof(Scalars, jvalid), &z, 4);
+      if (r != PIC_OK) return r;
+    }
+  }
   if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   h->step = step;
   return PIC_OK;
@@ -821,6 +842,13 @@ int pic_moments(pic_handle *h, pic_moments_out *out, int32_t reset) {
   if (out->ecnt) HIPCHK(h, hipMemcpy(out->ecnt, h->ws + L.ecnt, 8 * NSP * ng, hipMemcpyDeviceToHost));
   if (out->edf) HIPCHK(h, hipMemcpy(out->edf, h->ws + L.edf, 8 * NSP * NBIN, hipMemcpyDeviceToHost));
   if (out->iedf) HIPCHK(h, hipMemcpy(out->iedf, h->ws + L.iedf, 8 * NSP * 2 * NBIN, hipMemcpyDeviceToHost));
+  const size_t spc = h->cfg.steps_per_cycle;
+  if (out->current) HIPCHK(h, hipMemcpy(out->current, h->ws + L.jsum, 8 * spc, hipMemcpyDeviceToHost));
+  if (out->current_n) HIPCHK(h, hipMemcpy(out->current_n, h->ws + L.jcnt, 8 * spc, hipMemcpyDeviceToHost));
+  double jp[2];
+  HIPCHK(h, hipMemcpy(jp, h->ws + L.jpow, 16, hipMemcpyDeviceToHost));
+  out->power_sum = jp[0];
+  out->power_n = (int64_t)jp[1];
   if (reset) {
     HIPCHK(h, hipMemsetAsync(h->ws + L.sumQ, 0, 8 * NSP * nn, h->stream));
     HIPCHK(h, hipMemsetAsync(h->ws + L.sumphi, 0, 8 * nn, h->stream));
@@ -829,6 +857,9 @@ int pic_moments(pic_handle *h, pic_moments_out *out, int32_t reset) {
     HIPCHK(h, hipMemsetAsync(h->ws + L.edf, 0, 8 * NSP * NBIN, h->stream));
     HIPCHK(h, hipMemsetAsync(h->ws + L.iedf, 0, 8 * NSP * 2 * NBIN, h->stream));
     HIPCHK(h, hipMemsetAsync(h->ws + L.nacc, 0, 16, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->ws + L.jsum, 0, 8 * spc, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->ws + L.jcnt, 0, 8 * spc, h->stream));
+    HIPCHK(h, hipMemsetAsync(h->ws + L.jpow, 0, 16, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
   }
   return pic_sync(h);

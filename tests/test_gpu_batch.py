@@ -34,7 +34,8 @@ def _same(a, b, who):
             np.testing.assert_array_equal(a["parts"][s][k], b["parts"][s][k], err_msg=f"{who} species {s} {k}")
     np.testing.assert_array_equal(a["hist"], b["hist"], err_msg=who)
     np.testing.assert_array_equal(a["counters"], b["counters"], err_msg=who)
-    for k in ("sum_q", "sum_phi", "esum", "ecnt", "edf", "iedf", "nacc", "ndiag"):
+    for k in ("sum_q", "sum_phi", "esum", "ecnt", "edf", "iedf", "nacc", "ndiag", "current", "current_n",
+              "power_sum", "power_n"):
         np.testing.assert_array_equal(a["moments"][k], b["moments"][k], err_msg=f"{who} {k}")
 
 

@@ -352,3 +352,26 @@ def test_profile_loader_falls_back_to_uniform_on_invalid_input():
         a, b = H.by_id(g.get_particles(s)[0]), H.by_id(u.get_particles(s)[0])
         for k in ("cell", "off", "vx", "vy", "vz", "id", "cd"):
             np.testing.assert_array_equal(a[k], b[k])
+
+
+def test_current_density_and_power_match_oracle():
+    # section 3: displacement plus conduction current at the driven electrode per rf phase
+    d = I.config(1)
+    procs = I.make_processes()
+    o, g, st = _pair(d, procs, 0, event_capacity=0)
+    o.reset_moments()
+    g.moments(reset=True)
+    n = 60
+    o.step(n)
+    g.step(n)
+    co, mg = o.current(), g.moments()
+    assert np.array_equal(mg["current_n"], co["jcnt"]) and co["jcnt"].sum() == n - 1
+    jo, jg = co["jsum"], mg["current"]
+    dt = 1.0 / (d.f * d.steps_per_cycle)
+    one = H.QE * d.weight / dt                       # one superparticle charge per step
+    scale = np.max(np.abs(jo))
+    close = np.abs(jg - jo) <= 1e-6 * scale
+    assert np.mean(close) >= 0.9
+    assert np.all(np.abs(jg - jo) <= 1e-6 * scale + 2 * one)
+    assert mg["power_n"] == co["pn"]
+    assert abs(mg["power_sum"] - co["psum"]) <= 1e-5 * abs(d.U) * scale * n + 2 * abs(d.U) * one
