@@ -693,13 +693,29 @@ static void collide_ion(orc_sim *S, int s, int64_t i, double dts) {
   } else if (P->kind == ORC_NEUTRALIZE) {
     a->alive[i] = 0;
     S->kcell[(int)floor(a->xi[i])]++;
+  } else if (P->kind == ORC_ION_ELASTIC) {
+    /* Table 1 (8): elastic scattering on the sampled neutral, isotropic in the
+       centre-of-mass frame: v' = v_cm + M / (m + M) |g| n, n from the PROD draw */
+    uint32_t p0[4];
+    draw(S, s, id, S->step, ORC_P_PROD, 0, p0);
+    double M = P->target_mass, d[3];
+    double g[3] = {a->vx[i] - vt_chosen[0], a->vy[i] - vt_chosen[1], a->vz[i] - vt_chosen[2]};
+    double gm = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+    iso_dir(p0[0], p0[1], d);
+    double f = M / (m + M);
+    double vcm[3];
+    for (int k = 0; k < 3; ++k) vcm[k] = (m * (k == 0 ? a->vx[i] : k == 1 ? a->vy[i] : a->vz[i]) + M * vt_chosen[k]) / (m + M);
+    a->vx[i] = vcm[0] + f * gm * d[0];
+    a->vy[i] = vcm[1] + f * gm * d[1];
+    a->vz[i] = vcm[2] + f * gm * d[2];
   } else if (P->kind == ORC_DETACH) {
-    /* O- + O2(a) -> O3 + e: the electron carries the relative energy */
+    /* Table 1 (19), (20): O- + O2 -> O + O2 + e and O- + O2(a) -> O3 + e; the
+       electron carries the relative energy in excess of the threshold */
     uint32_t p0[4];
     draw(S, s, id, S->step, ORC_P_PROD, 0, p0);
     double d[3], v[3];
     iso_dir(p0[1], p0[2], d);
-    double vm = sqrt(2.0 * erel_chosen * Q_E / S->sp[ORC_E].mass);
+    double vm = sqrt(2.0 * fmax(erel_chosen - P->e_th, 0.0) * Q_E / S->sp[ORC_E].mass);
     v[0] = vm * d[0]; v[1] = vm * d[1]; v[2] = vm * d[2];
     int64_t k = add_product(S, ORC_E, a->xi[i], v, ((uint64_t)s << 32) | id);
     int64_t pb = 0;

@@ -31,7 +31,7 @@ extern "C" {
 
 enum { ORC_E = 0, ORC_POS = 1, ORC_NEG = 2, ORC_NSP = 3 };
 enum { ORC_ELASTIC = 0, ORC_EXCITE = 1, ORC_IONIZE = 2, ORC_ATTACH = 3,
-       ORC_CX = 4, ORC_NEUTRALIZE = 5, ORC_DETACH = 6 };
+       ORC_CX = 4, ORC_NEUTRALIZE = 5, ORC_DETACH = 6, ORC_ION_ELASTIC = 7 };
 enum { ORC_T_O2 = 0, ORC_T_O2A = 1, ORC_T_GRIDPOS = 2 };
 enum { ORC_P_LOAD = 1, ORC_P_CAND = 2, ORC_P_TARGET = 3, ORC_P_PROD = 4, ORC_P_PAIR = 5 };
 

@@ -17,7 +17,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
 SOURCES = [os.path.join(HERE, "oracle.c")]
 
-KIND = {"elastic": 0, "excite": 1, "ionize": 2, "attach": 3, "cx": 4, "neutralize": 5, "detach": 6}
+KIND = {"elastic": 0, "excite": 1, "ionize": 2, "attach": 3, "cx": 4, "neutralize": 5, "detach": 6,
+        "ion_elastic": 7}
 TARGET = {"O2": 0, "O2a": 1, "grid+": 2}
 F_EXT_FIELD, F_NO_COLL = 1, 2
 CD_MAX, CD_CAP, NBIN = 32767, 0x8000, 256

@@ -44,7 +44,7 @@ TABLE_N = 512
 
 # process kinds and collision targets (string names; each binding maps them
 # to its own enumeration)
-KINDS = ("elastic", "excite", "ionize", "attach", "cx", "neutralize", "detach")
+KINDS = ("elastic", "excite", "ionize", "attach", "cx", "neutralize", "detach", "ion_elastic")
 TARGETS = ("O2", "O2a", "grid+")   # background O2, metastable O2(a), O2+ grid density
 
 TABLE_SEED = 0x5EED0001
@@ -203,6 +203,36 @@ def make_processes(seed: int = TABLE_SEED, ad_eq1: bool = True) -> List[Process]
     procs.append(Process("O--ad", OMINUS, "detach", "O2a", eth, M_O2, power_law_table(s0, a, b, eth),
                          dict(sigma0=s0, a=a, b=b, e_th=eth)))
     return procs
+
+
+# Table 1 channels beyond the eight of the workloads (seeded with their own stream):
+# the two dissociation thresholds of rows (12), (13) as separate channels, O- elastic
+# scattering on O2 (8) and direct detachment O- + O2 -> O + O2 + e (19)
+_EXTRA_WINDOWS = {
+    "e-diss6.4": ("excite", ELECTRON, "O2", M_O2, (5e-21, 3e-20), (0.5, 2.0), (0.0, 0.4), (6.4, 6.4)),
+    "e-diss8.6": ("excite", ELECTRON, "O2", M_O2, (5e-21, 3e-20), (0.5, 2.0), (0.0, 0.4), (8.6, 8.6)),
+    "O--el": ("ion_elastic", OMINUS, "O2", M_O2, (1e-19, 5e-19), (0.0, 0.0), (0.0, 0.5), (0.0, 0.0)),
+    "O--dd": ("detach", OMINUS, "O2", M_O2, (1e-21, 1e-20), (0.5, 2.0), (0.0, 0.5), (1.5, 3.0)),
+}
+
+
+def make_processes_extended(seed: int = TABLE_SEED) -> List[Process]:
+    """Eleven channels: e elastic (7), vibrational (10), dissociation at 6.4 eV (12) and
+    8.6 eV (13), ionisation (21), attachment (18); O2+ charge exchange (9); O-
+    neutralisation (17), elastic (8), direct detachment (19), associative detachment (20)."""
+    base = {p.name: p for p in make_processes(seed)}
+    rng = np.random.Generator(np.random.PCG64(seed + 1))
+    extra = {}
+    for name, (kind, sp, tgt, tm, s0w, aw, bw, ew) in _EXTRA_WINDOWS.items():
+        s0 = float(math.exp(rng.uniform(math.log(s0w[0]), math.log(s0w[1]))))
+        a = float(rng.uniform(*aw))
+        b = float(rng.uniform(*bw))
+        eth = float(rng.uniform(*ew))
+        extra[name] = Process(name, sp, kind, tgt, eth, tm, power_law_table(s0, a, b, eth),
+                              dict(sigma0=s0, a=a, b=b, e_th=eth))
+    order = ["e-elastic", "e-vib", "e-diss6.4", "e-diss8.6", "e-ion", "e-att", "O2+-cx", "O--neut", "O--el",
+             "O--dd", "O--ad"]
+    return [base[n] if n in base else extra[n] for n in order]
 
 
 def constant_process(name, species, kind, target, sigma, e_th=0.0, target_mass=M_O2) -> Process:

@@ -684,3 +684,57 @@ def test_conduction_current_of_a_beam_into_the_driven_electrode():
     per_step = np.bincount(m, minlength=40)
     expect = QE * d.weight * per_step[1:25] / dt                         # samples of steps 1..24
     np.testing.assert_allclose(c["jsum"][:24], expect, rtol=1e-12, atol=0)
+
+
+# ---------------------------------------------------------------- Table 1 rows (8) and (19)
+def _cold_partner_setup(procs, nneg, p=2000.0):
+    # a neutral reservoir at 1e-12 K: the sampled partner is at rest to 1e-9 of the ion speeds used
+    d = I.config(1, L=0.025, ng=64, p=p, t_gas=1e-12, diag_every=0)
+    o = po.Oracle(d, species(0, 0, nneg), procs, flags=po.F_EXT_FIELD, e_ext=(0.0, 0.0))
+    return d, o
+
+
+def test_ion_elastic_scattering_is_isotropic_in_the_centre_of_mass_frame():
+    el = I.constant_process("el", 2, "ion_elastic", "O2", 5e-19)
+    n0 = 20000
+    d, o = _cold_partner_setup([el], n0)
+    v = math.sqrt(2 * 20.0 * QE / I.M_OMINUS)                       # 20 eV O- beam along +x
+    put(o, 2, np.linspace(20, 40, n0), np.full(n0, v))
+    empty(o, 0), empty(o, 1)
+    o.prepare(False)
+    o.log_events(True)
+    o.step(1)                                                          # one ion step
+    ev = o.events()
+    hit = set(ev[ev[:, 3] >= 0][:, 2].tolist())
+    st = o.get_particles(2)
+    sel = np.isin(st["id"], list(hit))
+    assert 0.05 * n0 < sel.sum() < 0.95 * n0
+    m, M = I.M_OMINUS, I.M_O2
+    vcm = m / (m + M) * v
+    rel = np.sqrt((st["vx"][sel] - vcm) ** 2 + st["vy"][sel] ** 2 + st["vz"][sel] ** 2)
+    np.testing.assert_allclose(rel, M / (m + M) * v, rtol=1e-5)     # |v' - v_cm| = M/(m+M) |g|
+    n = sel.sum()
+    for comp, mean in (("vx", vcm), ("vy", 0.0), ("vz", 0.0)):       # isotropic about the centre of mass
+        sd = M / (m + M) * v / math.sqrt(3 * n)
+        assert abs(st[comp][sel].mean() - mean) < 4.5 * sd
+    untouched = ~sel
+    np.testing.assert_allclose(st["vx"][untouched], v, rtol=1e-12)
+
+
+def test_direct_detachment_gives_the_relative_energy_above_threshold():
+    e_th = 2.0
+    dd = I.constant_process("dd", 2, "detach", "O2", 3e-19, e_th=e_th)
+    n0 = 20000
+    d, o = _cold_partner_setup([dd], n0)
+    e_lab = 15.0
+    v = math.sqrt(2 * e_lab * QE / I.M_OMINUS)
+    put(o, 2, np.linspace(20, 40, n0), np.full(n0, v))
+    empty(o, 0), empty(o, 1)
+    o.prepare(False)
+    o.step(1)
+    el = o.get_particles(0)
+    assert 0.05 * n0 < len(el["id"]) == n0 - o.count(2)
+    mu = I.M_OMINUS * I.M_O2 / (I.M_OMINUS + I.M_O2)
+    e_rel = 0.5 * mu * v * v / QE
+    ee = 0.5 * ME * (el["vx"] ** 2 + el["vy"] ** 2 + el["vz"] ** 2) / QE
+    np.testing.assert_allclose(ee, e_rel - e_th, rtol=1e-5)
