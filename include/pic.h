@@ -54,7 +54,9 @@ extern "C" {
 #define PIC_ATTACH 3       /* e + O2 -> O + O- (18) */
 #define PIC_CX 4           /* O2+ + O2 charge exchange (9) */
 #define PIC_NEUTRALIZE 5   /* O- + O2+ -> O + O2 (17), partner density from the grid */
-#define PIC_DETACH 6       /* O- + O2(a) -> O3 + e (20) */
+#define PIC_DETACH 6       /* O- + O2(a) -> O3 + e (20), O- + O2 -> O + O2 + e (19):
+                              the electron takes the relative energy above e_th */
+#define PIC_ION_ELASTIC 7  /* O- + O2 (8) or O2+ + O2 elastic: isotropic in the centre-of-mass frame */
 
 /* collision partners */
 #define PIC_T_O2 0         /* O2 background, n = p / kT */

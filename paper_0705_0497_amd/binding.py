@@ -19,7 +19,8 @@ PIC_OK, PIC_EINVAL, PIC_ECAPACITY, PIC_EIDOVERFLOW, PIC_ENAN, PIC_EHIP, PIC_ENOD
 PIC_EBUSY = -8
 PIC_WFALLBACK = 1
 TUNE_MAX = 32
-KIND = {"elastic": 0, "excite": 1, "ionize": 2, "attach": 3, "cx": 4, "neutralize": 5, "detach": 6}
+KIND = {"elastic": 0, "excite": 1, "ionize": 2, "attach": 3, "cx": 4, "neutralize": 5, "detach": 6,
+        "ion_elastic": 7}
 TARGET = {"O2": 0, "O2a": 1, "grid+": 2}
 F_EXT_FIELD, F_NO_COLL = 1, 2
 NBIN, NCOUNT = 256, 40

@@ -21,7 +21,8 @@ constexpr uint32_t W_CAP = 0x8000u;
 constexpr int W_CD_SHIFT = 16;
 constexpr int32_t W_DEAD = -1;
 
-enum { K_ELASTIC = 0, K_EXCITE = 1, K_IONIZE = 2, K_ATTACH = 3, K_CX = 4, K_NEUTRALIZE = 5, K_DETACH = 6 };
+enum { K_ELASTIC = 0, K_EXCITE = 1, K_IONIZE = 2, K_ATTACH = 3, K_CX = 4, K_NEUTRALIZE = 5, K_DETACH = 6,
+       K_ION_ELASTIC = 7 };
 enum { T_O2 = 0, T_O2A = 1, T_GRIDPOS = 2 };
 enum { P_LOAD = 1, P_CAND = 2, P_TARGET = 3, P_PROD = 4, P_PAIR = 5 };
 enum { C_PUSH = 0, C_CAND = 3, C_NULL = 6, C_ABS0 = 9, C_ABSL = 12, C_BORN = 15, C_EVENT = 18,
@@ -65,6 +66,7 @@ struct ProcDev {
   float half_mu_e;                 // mu / (2 e) (energy from relative speed)
   float vt;                        // sqrt(k T / M) of the partner
   float tm_ratio;                  // 2 m / M (electron elastic loss)
+  float cmf;                       // M / (m + M): relative velocity share of the projectile in the CM frame
 };
 
 struct Sim {

@@ -606,7 +606,7 @@ __device__ void collide_ion(const Sim &S, int64_t step, const Cand &q, PushShare
   normals(t.x, t.y, z0, z1);
   normals(t.z, t.w, z2, z3);
   const float target = unif(c.y);
-  float acc = 0.0f, erel_c = 0.0f, pvx = 0.0f, pvy = 0.0f, pvz = 0.0f;
+  float acc = 0.0f, erel_c = 0.0f, pvx = 0.0f, pvy = 0.0f, pvz = 0.0f, eth_c = 0.0f, cmf = 0.0f;
   int chosen = -1, kind = 0;
   const int np = S.nproc_sp[S_];
   for (int k = 0; k < np; ++k) {
@@ -627,7 +627,7 @@ __device__ void collide_ion(const Sim &S, int64_t step, const Cand &q, PushShare
     const float sg = ec < pd.e_th ? 0.0f : tab_sigma(sh.tab + k * S.ntab, tab_pos(S, ec));
     acc = fmaf(dens * sg, g, acc);
     if (chosen < 0 && target < acc) {
-      chosen = pd.tab; kind = pd.kind; erel_c = erel; pvx = ux; pvy = uy; pvz = uz;
+      chosen = pd.tab; kind = pd.kind; erel_c = erel; pvx = ux; pvy = uy; pvz = uz; eth_c = pd.e_th; cmf = pd.cmf;
     }
   }
   log_event(S, step, S_, id, chosen);
@@ -642,15 +642,26 @@ __device__ void collide_ion(const Sim &S, int64_t step, const Cand &q, PushShare
     P.w[i] = cell;
     P.vx[i] = pvx; P.vy[i] = pvy; P.vz[i] = pvz;
     dep_lds(sh.Q, cell, off);
+  } else if (kind == K_ION_ELASTIC) {          // isotropic in the centre-of-mass frame (Table 1 (8))
+    const U4 p0 = draw(S, S_, id, step, P_PROD, 0);
+    float d0, d1, d2;
+    iso_dir(p0.x, p0.y, d0, d1, d2);
+    const float gx = vx - pvx, gy = vy - pvy, gz = vz - pvz;
+    const float gm = sqrtf(gx * gx + gy * gy + gz * gz) * cmf;
+    P.w[i] = cell;
+    P.vx[i] = fmaf(gm, d0, fmaf(-cmf, gx, vx));
+    P.vy[i] = fmaf(gm, d1, fmaf(-cmf, gy, vy));
+    P.vz[i] = fmaf(gm, d2, fmaf(-cmf, gz, vz));
+    dep_lds(sh.Q, cell, off);
   } else if (kind == K_NEUTRALIZE) {           // partner O2+ removed by the pairing rounds
     P.w[i] = W_DEAD;
     atomicAdd(&S.kleft[cell], 1);
     S.sc->pair_active = 1;
-  } else {                                     // K_DETACH: electron with the relative energy
+  } else {                                     // K_DETACH: electron with the relative energy above threshold
     const U4 p0 = draw(S, S_, id, step, P_PROD, 0);
     float d0, d1, d2;
     iso_dir(p0.y, p0.z, d0, d1, d2);
-    const float vm = sqrtf(S.two_e_m[0] * erel_c);
+    const float vm = sqrtf(S.two_e_m[0] * fmaxf(erel_c - eth_c, 0.0f));
     emit(S, 0, S_, id, cell | (int32_t)new_flight_f(S.inv_nd_ef, p0.w), off, vm * d0, vm * d1, vm * d2);
     dep_global(S.Q, cell, off);
     count_lanes(bc, C_BORN + 0);

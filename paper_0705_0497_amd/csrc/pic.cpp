@@ -150,8 +150,8 @@ int validate(const pic_config *c, const pic_species *sp, const pic_process *pr, 
     const pic_process &P = pr[p];
     if (P.species < 0 || P.species >= NSP) { msg = "process species out of range"; return PIC_EINVAL; }
     const bool ok = (P.species == 0 && P.kind >= PIC_ELASTIC && P.kind <= PIC_ATTACH) ||
-                    (P.species == 1 && P.kind == PIC_CX) ||
-                    (P.species == 2 && (P.kind == PIC_NEUTRALIZE || P.kind == PIC_DETACH));
+                    (P.species == 1 && (P.kind == PIC_CX || P.kind == PIC_ION_ELASTIC)) ||
+                    (P.species == 2 && (P.kind == PIC_NEUTRALIZE || P.kind == PIC_DETACH || P.kind == PIC_ION_ELASTIC));
     if (!ok) { msg = "process kind not valid for its species"; return PIC_EINVAL; }
     if (P.target < PIC_T_O2 || P.target > PIC_T_GRIDPOS || ((P.target == PIC_T_GRIDPOS) != (P.kind == PIC_NEUTRALIZE))) {
       msg = "process target invalid (the O2+ grid density is the partner of neutralisation only)"; return PIC_EINVAL;
@@ -387,6 +387,7 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
     d.half_mu_e = (float)(0.5 * mu / QE);
     d.vt = (float)std::sqrt(KB * c.t_gas / P.target_mass);
     d.tm_ratio = (float)(2.0 * sp[0].mass / P.target_mass);
+    d.cmf = (float)(P.target_mass / (sp[s].mass + P.target_mass));
   }
   unsigned char *ws = h->ws;
   S.Q = (unsigned long long *)(ws + L.Q);

@@ -375,3 +375,35 @@ def test_current_density_and_power_match_oracle():
     assert np.all(np.abs(jg - jo) <= 1e-6 * scale + 2 * one)
     assert mg["power_n"] == co["pn"]
     assert abs(mg["power_sum"] - co["psum"]) <= 1e-5 * abs(d.U) * scale * n + 2 * abs(d.U) * one
+
+
+@pytest.mark.parametrize("step0", [0, 20])
+def test_extended_channels_single_step_element_by_element(step0):
+    # eleven Table 1 channels, with O- elastic scattering (8) and direct detachment (19)
+    # made frequent so that one ion step exercises them on both sides
+    d = I.config(1)
+    procs = H.neutralising(I.make_processes_extended())
+    for k, p in enumerate(procs):
+        if p.name == "O--el":
+            p.sigma = p.sigma * 30.0
+        if p.name == "O--dd":                     # threshold within the thermal O- energies
+            procs[k] = I.Process("O--dd", 2, "detach", "O2", 0.02, I.M_O2,
+                                 I.power_law_table(1e-18, 1.0, 0.5, 0.02), {})
+    o, g, st = _pair(d, procs, step0, seed_steps=30)
+    o.log_events(True)
+    o.step(1)
+    g.step(1)
+    gev = g.events()
+    oev = o.events()
+    names = [p.name for p in procs]
+    for nm in ("O--el", "O--dd", "e-diss6.4", "e-diss8.6"):
+        assert np.sum(oev[:, 3] == names.index(nm)) >= 3, nm
+    bad, band = H.compare_events(gev, oev)
+    assert not bad, f"decisions differ outside the band: {bad[:10]}"
+    for s in range(3):
+        gs, nid_g = g.get_particles(s)
+        dx, dv = H.compare_states(gs, o.get_particles(s), d.species()[s], skip=band, s=s)
+        assert dx <= H.POS_TOL and dv <= H.VEL_TOL, (s, dx, dv)
+        np.testing.assert_array_equal(g.hist()[s], po.deposit_canonical(d.ng, gs["cell"], gs["off"]))
+    if not band:
+        np.testing.assert_array_equal(g.counters()[:po.C_CLAMP], o.counters()[:po.C_CLAMP])
