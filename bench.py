@@ -78,7 +78,8 @@ def main():
     ap.add_argument("--steps", type=int, default=50, help="timed rf cycles")
     ap.add_argument("--warmup", type=int, default=5, help="untimed rf cycles")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--block", type=int, default=1024,
+                    help="push block size (1024: one block per CU, half the partial histograms of 512)")
     ap.add_argument("--grid", type=int, default=0)
     ap.add_argument("--sort", choices=("compact", "cell"), default="compact",
                     help="periodic re-ordering: order-preserving compaction or counting sort by cell")
@@ -166,7 +167,7 @@ def main():
                    "electron_candidates": int(dc[C_CAND]), "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_push<512,0> electron push+MCC+deposit",
+                     "kernel": f"k_push<{args.block or 512},0> electron push+MCC+deposit",
                      "bytes_per_launch": per_launch, "mean_launch_ms": mean_ms},
     }
     if not args.no_cpu_baseline:

@@ -263,7 +263,7 @@ def test_full_size_sampled_single_step(cfg):
     from paper_0705_0497_amd.binding import Discharge
     d = I.config(cfg)
     procs = I.make_processes()
-    g = Discharge(d, procs, event_capacity=1 << 23)
+    g = Discharge(d, procs, event_capacity=1 << 23, block=1024)     # bench.py's push block
     g.load_uniform()
     warm = 2 * d.ksub - 1            # next step is an ion step with a sort just before it
     g.step(warm)
