@@ -33,6 +33,7 @@ struct orc_sim {
   orc_config c;
   orc_species sp[ORC_NSP];
   int32_t np;
+  int32_t neion;               /* processes of Table 1 (16), (22) */
   orc_process pr[MAXPROC];
   double *sigma;               /* np * table_n */
   double dx, dt, n_o2;
@@ -46,8 +47,8 @@ struct orc_sim {
   double *sumQ, *sumphi;
   int64_t nacc;
   int64_t *esum, *ecnt, *edf, *iedf, ndiag;
-  /* pairing work */
-  int64_t *kcell;
+  /* pairing work: partners to remove per cell (O2+, O-) */
+  int64_t *kcell, *kneg;
   /* event log */
   int32_t logon;
   int64_t nev, evcap, *ev;
@@ -144,32 +145,45 @@ static double reduced_mass(const orc_sim *S, int p) {
   return m * M / (m + M);
 }
 
-/* density of the collision partner of process p at position xi */
+/* number density [m^-3] of ion species s at node j from its charge histogram
+   (the end nodes own half a cell) */
+static double node_density(const orc_sim *S, int s, int j) {
+  double c = S->c.weight / TWO32 / S->dx;
+  const int64_t *Qs = S->Q + (size_t)s * (S->c.ng + 1);
+  return c * (double)Qs[j] * ((j == 0 || j == S->c.ng) ? 2.0 : 1.0);
+}
+
+/* density of the collision partner of process p at position xi; the ion
+   partners are read from the grid with the linear weighting of the deposit */
 static double target_density(const orc_sim *S, int p, double xi) {
   switch (S->pr[p].target) {
     case ORC_T_O2: return S->n_o2;
     case ORC_T_O2A: return S->c.c_meta * S->n_o2;
     default: {
+      int s = S->pr[p].target == ORC_T_GRIDPOS ? ORC_POS : ORC_NEG;
       int j = (int)floor(xi);
-      double w = xi - j, nj, nj1;
-      double c = S->c.weight / TWO32 / S->dx;
-      const int64_t *Qp = S->Q + (size_t)ORC_POS * (S->c.ng + 1);
-      nj = c * (double)Qp[j] * (j == 0 ? 2.0 : 1.0);
-      nj1 = c * (double)Qp[j + 1] * (j + 1 == S->c.ng ? 2.0 : 1.0);
-      return (1.0 - w) * nj + w * nj1;
+      double w = xi - j;
+      return (1.0 - w) * node_density(S, s, j) + w * node_density(S, s, j + 1);
     }
   }
 }
 
-/* max over the table intervals of sum_p n_p max(sigma_k, sigma_k+1) g(E_k+1) */
-static double nu_bound(const orc_sim *S, int s, const double *np_override) {
+/* Table 1 (16) and (22): electron collisions with the ions of the grid */
+static int is_eion(const orc_process *P) {
+  return P->species == ORC_E && (P->kind == ORC_RECOMB || P->kind == ORC_EDETACH);
+}
+
+/* max over the table intervals of sum_p n_p max(sigma_k, sigma_k+1) g(E_k+1),
+   over the processes of species s with (eion = 1) or without (eion = 0) the
+   electron-ion channels */
+static double nu_bound(const orc_sim *S, int s, const double *np_override, int eion) {
   int nt = S->c.table_n;
   double best = 0.0;
   for (int k = 0; k + 1 < nt; ++k) {
     double ek1 = S->c.table_emin * pow(S->c.table_emax / S->c.table_emin, (double)(k + 1) / (double)(nt - 1));
     double sum = 0.0;
     for (int p = 0; p < S->np; ++p) {
-      if (S->pr[p].species != s) continue;
+      if (S->pr[p].species != s || is_eion(&S->pr[p]) != eion) continue;
       const double *tab = S->sigma + (size_t)p * nt;
       double sm = fmax(tab[k], tab[k + 1]);
       double n = np_override ? np_override[p] : target_density(S, p, 0.0);
@@ -230,6 +244,7 @@ orc_sim *orc_create(const orc_config *cfg, const orc_species *sp, int32_t nproc,
   memcpy(S->sp, sp, sizeof(orc_species) * ORC_NSP);
   S->np = nproc;
   memcpy(S->pr, pr, sizeof(orc_process) * nproc);
+  for (int p = 0; p < nproc; ++p) S->neion += is_eion(&pr[p]);
   S->sigma = malloc(sizeof(double) * nproc * cfg->table_n);
   memcpy(S->sigma, sigma, sizeof(double) * nproc * cfg->table_n);
   S->dx = cfg->L / cfg->ng;
@@ -246,10 +261,11 @@ orc_sim *orc_create(const orc_config *cfg, const orc_species *sp, int32_t nproc,
   S->edf = calloc((size_t)ORC_NSP * ORC_NBIN, sizeof(int64_t));
   S->iedf = calloc((size_t)ORC_NSP * 2 * ORC_NBIN, sizeof(int64_t));
   S->kcell = calloc(cfg->ng, sizeof(int64_t));
+  S->kneg = calloc(cfg->ng, sizeof(int64_t));
   S->jsum = calloc(cfg->steps_per_cycle, sizeof(double));
   S->jcnt = calloc(cfg->steps_per_cycle, sizeof(int64_t));
-  S->numax[ORC_E] = nu_bound(S, ORC_E, NULL);
-  S->numax[ORC_POS] = nu_bound(S, ORC_POS, NULL);
+  S->numax[ORC_E] = nu_bound(S, ORC_E, NULL, 0);
+  S->numax[ORC_POS] = nu_bound(S, ORC_POS, NULL, 0);
   S->numax[ORC_NEG] = 0.0;   /* set at each ion step from the O2+ density */
   return S;
 }
@@ -262,7 +278,7 @@ void orc_destroy(orc_sim *S) {
     free(a->capped); free(a->alive); free(a->pkey); free(a->pband);
   }
   free(S->sigma); free(S->Q); free(S->phi); free(S->E); free(S->sumQ); free(S->sumphi);
-  free(S->esum); free(S->ecnt); free(S->edf); free(S->iedf); free(S->kcell); free(S->ev);
+  free(S->esum); free(S->ecnt); free(S->edf); free(S->iedf); free(S->kcell); free(S->kneg); free(S->ev);
   free(S->jsum); free(S->jcnt);
   free(S);
 }
@@ -598,7 +614,7 @@ static void collide_electron(orc_sim *S, int64_t i) {
   double acc = 0.0;
   int chosen = -1;
   for (int p = 0; p < S->np; ++p) {
-    if (S->pr[p].species != ORC_E) continue;
+    if (S->pr[p].species != ORC_E || is_eion(&S->pr[p])) continue;
     acc += target_density(S, p, a->xi[i]) * orc_sigma(S, p, ec) * g;
     if (fabs(target - acc) < 1e-6 * S->numax[ORC_E]) band |= 1;
     if (chosen < 0 && target < acc) chosen = p;
@@ -760,35 +776,105 @@ static void push_species(orc_sim *S, int s, int64_t nstart) {
   }
 }
 
-/* one O2+ removed per neutralised O-, from the same cell: the pre-step O2+ with
-   the smallest (pairing draw, id); at most pair_rounds per cell */
-static void pairing(orc_sim *S, int64_t nstart_pos) {
+/* partners of the ion removals of this ion step: per cell j, k[j] ions of
+   species s that were there before the step and are alive after its pushes,
+   each the one with the smallest (pairing draw, id); at most pair_rounds per
+   cell, the rest counted as a deficit.  O2+ partners of neutralisation (17) and
+   recombination (16), O- partners of electron-impact detachment (22). */
+static void pairing(orc_sim *S, int s, int64_t nstart_s, int64_t *k_cell, int c_paired, int c_deficit) {
   int ng = S->c.ng;
-  orc_store *a = &S->st[ORC_POS];
-  int64_t *Qp = S->Q + (size_t)ORC_POS * (ng + 1);
+  orc_store *a = &S->st[s];
   for (int j = 0; j < ng; ++j) {
-    int64_t k = S->kcell[j];
+    int64_t k = k_cell[j];
     if (k == 0) continue;
     int64_t want = k < S->c.pair_rounds ? k : S->c.pair_rounds;
     for (int64_t r = 0; r < want; ++r) {
       uint64_t best = UINT64_MAX;
       int64_t bi = -1;
-      for (int64_t i = 0; i < nstart_pos; ++i) {
+      for (int64_t i = 0; i < nstart_s; ++i) {
         if (!a->alive[i] || (int)floor(a->xi[i]) != j) continue;
         uint32_t d[4];
-        draw(S, ORC_POS, a->id[i], S->step, ORC_P_PAIR, 0, d);
+        draw(S, s, a->id[i], S->step, ORC_P_PAIR, 0, d);
         uint64_t key = ((uint64_t)d[0] << 32) | a->id[i];
         if (key < best) { best = key; bi = i; }
       }
       if (bi < 0) break;
       a->alive[bi] = 0;
-      S->cnt[ORC_C_PAIRED]++;
+      S->cnt[c_paired]++;
       --k;
     }
-    S->cnt[ORC_C_DEFICIT] += k > 0 ? k : 0;
-    S->kcell[j] = 0;
+    S->cnt[c_deficit] += k > 0 ? k : 0;
+    k_cell[j] = 0;
   }
-  (void)Qp;
+}
+
+/* Table 1 (16) e + O2+ -> O + O and (22) e + O- -> O + 2e.  Once per ion step,
+   after the electron push, every electron present at the start of the step is
+   a candidate with probability 1 - exp(-nu_ei ksub dt): nu_ei bounds
+   sum_p n_p(x) sigma_p(E) g over the gap with the largest node densities of the
+   field solve, the ion taken at rest (g = electron speed, E its energy).  The
+   channel follows from u nu_ei against the running sum at the electron's
+   position.  (16): electron and an O2+ of its cell removed.  (22): E - E_th
+   shared by the two electrons as (1 - r, r), both isotropic; an O- of the cell
+   removed.  Partners go to the pairing. */
+static void eion_pass(orc_sim *S, int64_t n_e) {
+  int nn = S->c.ng + 1;
+  double nmax[ORC_NSP] = {0.0, 0.0, 0.0};
+  for (int s = ORC_POS; s <= ORC_NEG; ++s)
+    for (int j = 0; j < nn; ++j) nmax[s] = fmax(nmax[s], node_density(S, s, j));
+  double nover[MAXPROC];
+  for (int p = 0; p < S->np; ++p)
+    nover[p] = !is_eion(&S->pr[p]) ? 0.0 : nmax[S->pr[p].target == ORC_T_GRIDPOS ? ORC_POS : ORC_NEG];
+  double nu = nu_bound(S, ORC_E, nover, 1);
+  double pnull = 1.0 - exp(-nu * S->dt * S->c.ksub);
+  double me = S->sp[ORC_E].mass;
+  orc_store *a = &S->st[ORC_E];
+  for (int64_t i = 0; i < n_e; ++i) {
+    if (!a->alive[i]) continue;
+    uint32_t id = a->id[i], c[4];
+    int64_t band = 0;
+    draw(S, ORC_E, id, S->step, ORC_P_EION, 0, c);
+    double u0 = unif(c[0]);
+    if (fabs(u0 - pnull) < 1e-6) band |= 8;
+    if (!(u0 < pnull)) { if (band) log_event(S, ORC_EV_EION, id, -4, band, 0); continue; }
+    S->cnt[ORC_C_EICAND]++;
+    double v2 = a->vx[i] * a->vx[i] + a->vy[i] * a->vy[i] + a->vz[i] * a->vz[i];
+    double e = 0.5 * me * v2 / Q_E;
+    double ec = clamp_e(S, e);
+    double g = sqrt(2.0 * ec * Q_E / me);
+    double target = unif(c[1]) * nu, acc = 0.0;
+    int chosen = -1;
+    for (int p = 0; p < S->np; ++p) {
+      if (!is_eion(&S->pr[p])) continue;
+      acc += target_density(S, p, a->xi[i]) * orc_sigma(S, p, ec) * g;
+      if (fabs(target - acc) < 1e-6 * nu) band |= 1;
+      if (chosen < 0 && target < acc) chosen = p;
+    }
+    log_event(S, ORC_EV_EION, id, chosen, band, 0);
+    if (chosen < 0) { S->cnt[ORC_C_EINULL]++; continue; }
+    S->cnt[ORC_C_EVENT + chosen]++;
+    int j = (int)floor(a->xi[i]);
+    if (S->pr[chosen].kind == ORC_RECOMB) {
+      a->alive[i] = 0;
+      S->kcell[j]++;
+    } else {
+      uint32_t p0[4];
+      draw(S, ORC_E, id, S->step, ORC_P_EION, 1, p0);
+      double er = fmax(e - S->pr[chosen].e_th, 0.0), r = unif(p0[0]);
+      double d[3], d2[3], v[3];
+      iso_dir(c[2], c[3], d);
+      double vn = sqrt(2.0 * (1.0 - r) * er * Q_E / me);
+      a->vx[i] = vn * d[0]; a->vy[i] = vn * d[1]; a->vz[i] = vn * d[2];
+      iso_dir(p0[1], p0[2], d2);
+      double v2m = sqrt(2.0 * r * er * Q_E / me);
+      v[0] = v2m * d2[0]; v[1] = v2m * d2[1]; v[2] = v2m * d2[2];
+      int64_t k = add_product(S, ORC_E, a->xi[i], v, ((uint64_t)ORC_EV_EION << 32) | id);
+      int64_t pb = 0;
+      new_flight(S, p0[3], &a->cd[k], &a->capped[k], &pb);
+      a->pband[k] = pb != 0;
+      S->kneg[j]++;
+    }
+  }
 }
 
 /* ids of this step's products: per species, next_id + rank in (parent species, parent id) */
@@ -863,6 +949,7 @@ static void one_step(orc_sim *S) {
   /* 2. electrons, every step */
   push_species(S, ORC_E, nstart[ORC_E]);
   int ion_step = (S->step % S->c.ksub) == 0;
+  if (ion_step && S->neion > 0 && !(S->c.flags & ORC_F_NO_COLL)) eion_pass(S, nstart[ORC_E]);
   if (ion_step) {
     /* 3. O2+ then O- with dt_i = ksub dt and this step's field */
     push_species(S, ORC_POS, nstart[ORC_POS]);
@@ -877,9 +964,10 @@ static void one_step(orc_sim *S) {
     double nover[MAXPROC];
     for (int p = 0; p < S->np; ++p)
       nover[p] = S->pr[p].target == ORC_T_GRIDPOS ? nmax : target_density(S, p, 0.0);
-    S->numax[ORC_NEG] = nu_bound(S, ORC_NEG, nover);
+    S->numax[ORC_NEG] = nu_bound(S, ORC_NEG, nover, 0);
     push_species(S, ORC_NEG, nstart[ORC_NEG]);
-    pairing(S, nstart[ORC_POS]);
+    pairing(S, ORC_POS, nstart[ORC_POS], S->kcell, ORC_C_PAIRED, ORC_C_DEFICIT);
+    pairing(S, ORC_NEG, nstart[ORC_NEG], S->kneg, ORC_C_PAIRED_NEG, ORC_C_DEFICIT_NEG);
     deposit_species(S, ORC_POS);
     deposit_species(S, ORC_NEG);
   } else {

@@ -31,9 +31,13 @@ extern "C" {
 
 enum { ORC_E = 0, ORC_POS = 1, ORC_NEG = 2, ORC_NSP = 3 };
 enum { ORC_ELASTIC = 0, ORC_EXCITE = 1, ORC_IONIZE = 2, ORC_ATTACH = 3,
-       ORC_CX = 4, ORC_NEUTRALIZE = 5, ORC_DETACH = 6, ORC_ION_ELASTIC = 7 };
-enum { ORC_T_O2 = 0, ORC_T_O2A = 1, ORC_T_GRIDPOS = 2 };
-enum { ORC_P_LOAD = 1, ORC_P_CAND = 2, ORC_P_TARGET = 3, ORC_P_PROD = 4, ORC_P_PAIR = 5 };
+       ORC_CX = 4, ORC_NEUTRALIZE = 5, ORC_DETACH = 6, ORC_ION_ELASTIC = 7,
+       ORC_RECOMB = 8,      /* e + O2+ -> O + O, Table 1 (16) */
+       ORC_EDETACH = 9 };   /* e + O- -> O + 2e, Table 1 (22) */
+enum { ORC_T_O2 = 0, ORC_T_O2A = 1, ORC_T_GRIDPOS = 2, ORC_T_GRIDNEG = 3 };
+enum { ORC_P_LOAD = 1, ORC_P_CAND = 2, ORC_P_TARGET = 3, ORC_P_PROD = 4, ORC_P_PAIR = 5, ORC_P_EION = 6 };
+/* species field of the event records of the electron-ion test */
+enum { ORC_EV_EION = 3 };
 
 /* flags */
 #define ORC_F_EXT_FIELD  1   /* field = e_ext0 + e_ext1 (x - L/2) instead of Poisson */
@@ -56,7 +60,11 @@ enum {
   ORC_C_DEFICIT = 35,  /* neutralisations without a partner */
   ORC_C_CLAMP = 36,    /* energies clamped to the table range */
   ORC_C_REDRAW = 37,   /* capped free flights redrawn */
-  ORC_NCOUNT = 40
+  ORC_C_EICAND = 38,   /* electron-ion candidates */
+  ORC_C_EINULL = 39,   /* electron-ion null collisions */
+  ORC_C_PAIRED_NEG = 40,   /* O- removed as partners of electron-impact detachment */
+  ORC_C_DEFICIT_NEG = 41,  /* electron-impact detachments without an O- partner */
+  ORC_NCOUNT = 44
 };
 
 typedef struct {
@@ -138,7 +146,8 @@ int64_t orc_get_moments(const orc_sim *S, double *sumQ, double *sumphi, int64_t 
 void orc_get_current(const orc_sim *S, double *jsum, int64_t *jcnt, double *psum, int64_t *pn);
 
 /* event log: records of 6 int64 {step, species, id, code, band, aux};
-   code >= 0 process index, -1 null, -2 capped redraw, -3 absorbed */
+   code >= 0 process index, -1 null, -2 capped redraw, -3 absorbed, -4 candidate
+   test in the band; species ORC_EV_EION for the electron-ion test of an electron */
 void orc_log_events(orc_sim *S, int32_t on);
 int64_t orc_get_events(orc_sim *S, int64_t max, int64_t *rec);
 

@@ -18,13 +18,15 @@ LIB_PATH = os.path.join(HERE, "liboracle.so")
 SOURCES = [os.path.join(HERE, "oracle.c")]
 
 KIND = {"elastic": 0, "excite": 1, "ionize": 2, "attach": 3, "cx": 4, "neutralize": 5, "detach": 6,
-        "ion_elastic": 7}
-TARGET = {"O2": 0, "O2a": 1, "grid+": 2}
+        "ion_elastic": 7, "recomb": 8, "edetach": 9}
+TARGET = {"O2": 0, "O2a": 1, "grid+": 2, "grid-": 3}
+EV_EION = 3          # species field of the event records of the electron-ion test
 F_EXT_FIELD, F_NO_COLL = 1, 2
 CD_MAX, CD_CAP, NBIN = 32767, 0x8000, 256
 # counters
 C_PUSH, C_CAND, C_NULL, C_ABS0, C_ABSL, C_BORN, C_EVENT = 0, 3, 6, 9, 12, 15, 18
-C_PAIRED, C_DEFICIT, C_CLAMP, C_REDRAW, NCOUNT = 34, 35, 36, 37, 40
+C_PAIRED, C_DEFICIT, C_CLAMP, C_REDRAW = 34, 35, 36, 37
+C_EICAND, C_EINULL, C_PAIRED_NEG, C_DEFICIT_NEG, NCOUNT = 38, 39, 40, 41, 44
 
 
 def build(force: bool = True) -> str:

@@ -44,8 +44,8 @@ TABLE_N = 512
 
 # process kinds and collision targets (string names; each binding maps them
 # to its own enumeration)
-KINDS = ("elastic", "excite", "ionize", "attach", "cx", "neutralize", "detach", "ion_elastic")
-TARGETS = ("O2", "O2a", "grid+")   # background O2, metastable O2(a), O2+ grid density
+KINDS = ("elastic", "excite", "ionize", "attach", "cx", "neutralize", "detach", "ion_elastic", "recomb", "edetach")
+TARGETS = ("O2", "O2a", "grid+", "grid-")   # background O2, metastable O2(a), O2+ / O- grid densities
 
 TABLE_SEED = 0x5EED0001
 
@@ -233,6 +233,41 @@ def make_processes_extended(seed: int = TABLE_SEED) -> List[Process]:
     order = ["e-elastic", "e-vib", "e-diss6.4", "e-diss8.6", "e-ion", "e-att", "O2+-cx", "O--neut", "O--el",
              "O--dd", "O--ad"]
     return [base[n] if n in base else extra[n] for n in order]
+
+
+# The remaining Table 1 channels with a collision partner other than a
+# charged particle of the same kind (rows 1-6 are Coulomb scattering, not
+# modelled), seeded with a third stream: Rydberg (11), a1Delta_g (14) and
+# b1Sigma_g (15) excitation at the textbook excitation energies of O2 (the
+# Rydberg window a guess), dissociative recombination (16, falling as 1/E) and
+# electron-impact detachment of O- (22, above the electron affinity of O).
+_FULL_WINDOWS = {
+    "e-ryd": ("excite", ELECTRON, "O2", M_O2, (1e-21, 1e-20), (0.5, 2.0), (0.0, 0.5), (8.5, 9.5)),
+    "e-a1": ("excite", ELECTRON, "O2", M_O2, (5e-22, 3e-21), (0.5, 2.0), (0.5, 1.5), (0.977, 0.977)),
+    "e-b1": ("excite", ELECTRON, "O2", M_O2, (1e-22, 1e-21), (0.5, 2.0), (0.5, 1.5), (1.627, 1.627)),
+    "e-recomb": ("recomb", ELECTRON, "grid+", M_O2PLUS, (1e-20, 1e-19), (0.0, 0.0), (1.0, 1.5), (0.0, 0.0)),
+    "e-edet": ("edetach", ELECTRON, "grid-", M_OMINUS, (1e-20, 1e-19), (1.0, 2.0), (0.0, 0.5), (1.461, 1.461)),
+}
+
+
+def make_processes_full(seed: int = TABLE_SEED) -> List[Process]:
+    """All sixteen channels of Table 1 that have a model here: e + O2 elastic (7),
+    vibrational (10), Rydberg (11), dissociation at 6.4 eV (12) and 8.6 eV (13),
+    a1Delta_g (14), b1Sigma_g (15), ionisation (21), attachment (18); e + O2+
+    recombination (16); e + O- detachment (22); O2+ charge exchange (9); O-
+    neutralisation (17), elastic (8), direct (19) and associative (20) detachment."""
+    ext = {p.name: p for p in make_processes_extended(seed)}
+    rng = np.random.Generator(np.random.PCG64(seed + 2))
+    for name, (kind, sp, tgt, tm, s0w, aw, bw, ew) in _FULL_WINDOWS.items():
+        s0 = float(math.exp(rng.uniform(math.log(s0w[0]), math.log(s0w[1]))))
+        a = float(rng.uniform(*aw))
+        b = float(rng.uniform(*bw))
+        eth = float(rng.uniform(*ew))
+        ext[name] = Process(name, sp, kind, tgt, eth, tm, power_law_table(s0, a, b, eth),
+                            dict(sigma0=s0, a=a, b=b, e_th=eth))
+    order = ["e-elastic", "e-vib", "e-ryd", "e-diss6.4", "e-diss8.6", "e-a1", "e-b1", "e-ion", "e-att",
+             "e-recomb", "e-edet", "O2+-cx", "O--neut", "O--el", "O--dd", "O--ad"]
+    return [ext[n] for n in order]
 
 
 def constant_process(name, species, kind, target, sigma, e_th=0.0, target_mass=M_O2) -> Process:

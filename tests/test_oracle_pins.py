@@ -738,3 +738,115 @@ def test_direct_detachment_gives_the_relative_energy_above_threshold():
     e_rel = 0.5 * mu * v * v / QE
     ee = 0.5 * ME * (el["vx"] ** 2 + el["vy"] ** 2 + el["vz"] ** 2) / QE
     np.testing.assert_allclose(ee, e_rel - e_th, rtol=1e-5)
+
+
+# ---------------------------------------------------------------- Table 1 rows (16) and (22)
+G1 = math.sqrt(2 * QE / ME)        # electron speed at 1 eV
+
+
+def _ions_on_cell_centres(o, s, ng, k):
+    """k ions of species s at the centre of every cell, at rest: the linear-weighting
+    deposit gives every node (the end nodes own half a cell) exactly k w / dx."""
+    xi = np.repeat(np.arange(ng) + 0.5, k)
+    put(o, s, xi, np.zeros(len(xi)))
+
+
+def _eion_setup(procs, n_e=400000, k=64, n_ion=3.67e19, e_ev=10.0, ng=64, seed=11, pos=True, neg=True):
+    """Electrons moving along y at e_ev (no field, no gas: position and energy stay put)
+    over uniform O2+ and / or O- of density n_ion; one ion step."""
+    d = I.config(1, L=0.025, ng=ng, p=0.0, diag_every=0, pair_rounds=64, n_plus0=n_ion,
+                 counts=(n_e, k * ng, k * ng))
+    sp = species(n_e, k * ng, k * ng)
+    o = po.Oracle(d, sp, procs, flags=po.F_EXT_FIELD, e_ext=(0.0, 0.0))
+    rng = np.random.default_rng(seed)
+    v = math.sqrt(2 * e_ev * QE / ME)
+    put(o, 0, rng.uniform(0, ng, n_e), np.zeros(n_e), vy=np.full(n_e, v))
+    _ions_on_cell_centres(o, 1, ng, k) if pos else empty(o, 1)
+    _ions_on_cell_centres(o, 2, ng, k) if neg else empty(o, 2)
+    o.prepare(False)
+    dx = d.L / ng
+    assert abs(k * d.weight / dx / n_ion - 1) < 1e-12
+    return d, o, v
+
+
+def _sqrt_law(sigma1, e_th=0.0):
+    # sigma = sigma1 (E / 1 eV)^(-1/2): sigma g = sigma1 G1 at every energy, so the
+    # bound of the test equals the real rate and no null collision is drawn
+    return I.power_law_table(sigma1, 0.0, 0.5, e_th)
+
+
+def test_recombination_and_electron_detachment_follow_competing_exponentials():
+    """(16) and (22) against the closed form of two competing first-order losses
+    over one ion step T = ksub dt: P(16 first) = r16 / (r16 + r22) (1 - exp(-(r16 + r22) T)),
+    r = n sigma g (density k w / dx of the ions on the cell centres)."""
+    s16, s22 = 1.0e-19, 0.5e-19
+    rec = I.Process("rec", 0, "recomb", "grid+", 0.0, I.M_O2PLUS, _sqrt_law(s16), {})
+    edt = I.Process("edt", 0, "edetach", "grid-", 1.461, I.M_OMINUS, _sqrt_law(s22, 1.461), {})
+    n_e, k, n_ion = 400000, 64, 3.67e19
+    d, o, v = _eion_setup([rec, edt], n_e=n_e, k=k, n_ion=n_ion)
+    o.step(1)
+    c = o.counters()
+    T = d.ksub * d.dt
+    r16, r22 = n_ion * s16 * G1, n_ion * s22 * G1
+    p_any = 1.0 - math.exp(-(r16 + r22) * T)
+    k16, k22 = c[po.C_EVENT + 0], c[po.C_EVENT + 1]
+    assert binom_ok(k16, n_e, p_any * r16 / (r16 + r22))
+    assert binom_ok(k22, n_e, p_any * r22 / (r16 + r22))
+    assert binom_ok(c[po.C_EICAND], n_e, p_any, z=5.0)
+    # one partner per event from the event's cell, and nothing else moves
+    assert c[po.C_PAIRED] == k16 and c[po.C_PAIRED_NEG] == k22
+    assert c[po.C_DEFICIT] == 0 and c[po.C_DEFICIT_NEG] == 0
+    assert o.count(0) == n_e - k16 + k22
+    assert o.count(1) == k * d.ng - k16 and o.count(2) == k * d.ng - k22
+    assert c[po.C_BORN + 0] == k22
+
+
+def test_electron_detachment_conserves_energy_minus_the_threshold():
+    """(22): the two electrons share E - E_th, both directions isotropic."""
+    e_th, e0 = 1.461, 10.0
+    edt = I.Process("edt", 0, "edetach", "grid-", e_th, I.M_OMINUS, _sqrt_law(2e-19, e_th), {})
+    n_e = 200000
+    d, o, v = _eion_setup([edt], n_e=n_e, e_ev=e0, pos=False)
+    o.step(1)
+    k22 = o.counters()[po.C_EVENT + 0]
+    assert k22 > 1000
+    el = o.get_particles(0)
+    ee = 0.5 * ME * (el["vx"] ** 2 + el["vy"] ** 2 + el["vz"] ** 2) / QE
+    assert len(ee) == n_e + k22
+    assert abs(ee.sum() - (n_e * e0 - k22 * e_th)) < 1e-9 * n_e * e0
+    new = el["id"] >= n_e                        # the detached electrons
+    assert new.sum() == k22
+    sp = np.sqrt(ee[new] * 2 * QE / ME)
+    dirs = np.stack([el["vx"][new], el["vy"][new], el["vz"][new]]) / np.maximum(sp, 1e-30)
+    assert np.all(np.abs(dirs.mean(axis=1)) < 4 / math.sqrt(3 * k22))
+    np.testing.assert_allclose((dirs ** 2).mean(axis=1), 1 / 3, atol=4 * math.sqrt(4 / 45 / k22))
+    # the shares: the new electron's fraction r of E0 - E_th is uniform on (0, 1)
+    r = ee[new] / (e0 - e_th)
+    assert abs(r.mean() - 0.5) < 4 * math.sqrt(1 / 12 / k22)
+
+
+def test_recombination_removes_a_partner_from_the_electrons_cell():
+    """(16) with the O2+ of one cell only: only electrons next to it recombine, and
+    their partners come from that cell, at most pair_rounds per ion step."""
+    rec = I.Process("rec", 0, "recomb", "grid+", 0.0, I.M_O2PLUS, _sqrt_law(4e-19), {})
+    d, o, v = _eion_setup([rec], n_e=100000, k=64, neg=False)
+    # move all O2+ into cell 5: the node densities the test sees change, the electrons of cell 5
+    # find partners, the others do not
+    put(o, 1, np.full(64 * 64, 5.5), np.zeros(64 * 64))
+    o.prepare(False)
+    el0 = o.get_particles(0)
+    o.step(1)
+    c = o.counters()
+    k16 = c[po.C_EVENT + 0]
+    assert k16 > 0
+    assert c[po.C_PAIRED] + c[po.C_DEFICIT] == k16
+    survivors = set(o.get_particles(0)["id"].tolist())
+    gone = [i for i in el0["id"].tolist() if i not in survivors]
+    cells = np.floor(el0["xi"][np.isin(el0["id"], gone)]).astype(int)
+    assert len(gone) == k16
+    # only electrons near cell 5 (nodes 5, 6 carry the density) can recombine; partners
+    # come from cell 5 only, at most pair_rounds of them per ion step
+    assert set(cells.tolist()) <= {4, 5, 6}
+    n5 = int(np.sum(cells == 5))
+    assert n5 > d.pair_rounds and c[po.C_PAIRED] == d.pair_rounds
+    assert o.count(1) == 64 * 64 - d.pair_rounds
