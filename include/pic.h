@@ -57,11 +57,19 @@ extern "C" {
 #define PIC_DETACH 6       /* O- + O2(a) -> O3 + e (20), O- + O2 -> O + O2 + e (19):
                               the electron takes the relative energy above e_th */
 #define PIC_ION_ELASTIC 7  /* O- + O2 (8) or O2+ + O2 elastic: isotropic in the centre-of-mass frame */
+/* electron collisions with the ions of the grid, tested once per ion step after
+   the electron push (probability 1 - exp(-nu_ei ksub dt), nu_ei from the largest
+   ion node densities of the field solve, the ion at rest); the struck ion is the
+   pairing partner in the electron's cell.  Single discharges only (not batches). */
+#define PIC_RECOMB 8       /* e + O2+ -> O + O (16): electron and an O2+ removed; target PIC_T_GRIDPOS */
+#define PIC_EDETACH 9      /* e + O- -> O + 2e (22): E - e_th shared (1 - r, r) by the two electrons,
+                              isotropic; an O- removed; target PIC_T_GRIDNEG */
 
 /* collision partners */
 #define PIC_T_O2 0         /* O2 background, n = p / kT */
 #define PIC_T_O2A 1        /* metastable O2(a), n = C p / kT */
 #define PIC_T_GRIDPOS 2    /* O2+ density of the simulation grid */
+#define PIC_T_GRIDNEG 3    /* O- density of the simulation grid */
 
 /* configuration flags (test hooks) */
 #define PIC_F_EXT_FIELD 1  /* E(x) = e_ext0 + e_ext1 (x - L/2) replaces the Poisson field */
@@ -72,7 +80,7 @@ extern "C" {
 #define PIC_SORT_COMPACT 1 /* order-preserving compaction */
 
 #define PIC_NBIN 256       /* log energy bins from 1e-3 to 1e3 eV */
-#define PIC_NCOUNT 40      /* counters, layout below */
+#define PIC_NCOUNT 44      /* counters, layout below */
 
 /* counter layout (int64): index + species or + process */
 #define PIC_C_PUSH 0       /* +s particles pushed */
@@ -82,10 +90,14 @@ extern "C" {
 #define PIC_C_ABSL 12      /* +s absorbed at x = L */
 #define PIC_C_BORN 15      /* +s products born */
 #define PIC_C_EVENT 18     /* +p real collisions of process p (p < 16) */
-#define PIC_C_PAIRED 34    /* O2+ removed as neutralisation partners */
-#define PIC_C_DEFICIT 35   /* neutralisations that found no partner */
+#define PIC_C_PAIRED 34    /* O2+ removed as partners of neutralisation and recombination */
+#define PIC_C_DEFICIT 35   /* neutralisations and recombinations that found no O2+ partner */
 #define PIC_C_CLAMP 36     /* energies clamped into the table range */
 #define PIC_C_REDRAW 37    /* capped free flights redrawn */
+#define PIC_C_EICAND 38    /* electron-ion candidates */
+#define PIC_C_EINULL 39    /* electron-ion null collisions */
+#define PIC_C_PAIRED_NEG 40  /* O- removed as partners of electron-impact detachment */
+#define PIC_C_DEFICIT_NEG 41 /* electron-impact detachments that found no O- partner */
 
 typedef struct pic_config {
   double L;                /* gap [m], > 0 */
@@ -123,7 +135,7 @@ typedef struct pic_species {
 
 typedef struct pic_process {
   int32_t species;         /* projectile species index */
-  int32_t kind;            /* PIC_ELASTIC .. PIC_DETACH */
+  int32_t kind;            /* PIC_ELASTIC .. PIC_EDETACH; at most 12 processes per species */
   int32_t target;          /* PIC_T_* */
   double e_th;             /* threshold [eV]; sigma = 0 below it */
   double target_mass;      /* partner mass [kg] */
@@ -240,7 +252,8 @@ int pic_get_field(pic_handle *h, double *phi, float *e);
 int pic_get_counters(pic_handle *h, int64_t *out);
 
 /* Collision event log (config event_capacity > 0): records of 4 int64
-   {step, species, id, code}; code >= 0 process index, -1 null collision,
+   {step, species, id, code} (species 3: the electron-ion test of electron id);
+   code >= 0 process index, -1 null collision,
    -2 capped flight redrawn, -3 absorbed (electrode in the id's record aux is
    not kept).  Returns the number of events since the last clear in *n; copies
    min(*n, max) records.  clear != 0 empties the log. */

@@ -20,12 +20,14 @@ PIC_EBUSY = -8
 PIC_WFALLBACK = 1
 TUNE_MAX = 32
 KIND = {"elastic": 0, "excite": 1, "ionize": 2, "attach": 3, "cx": 4, "neutralize": 5, "detach": 6,
-        "ion_elastic": 7}
-TARGET = {"O2": 0, "O2a": 1, "grid+": 2}
+        "ion_elastic": 7, "recomb": 8, "edetach": 9}
+TARGET = {"O2": 0, "O2a": 1, "grid+": 2, "grid-": 3}
+EV_EION = 3          # species field of the event records of the electron-ion test
 F_EXT_FIELD, F_NO_COLL = 1, 2
-NBIN, NCOUNT = 256, 40
+NBIN, NCOUNT = 256, 44
 C_PUSH, C_CAND, C_NULL, C_ABS0, C_ABSL, C_BORN, C_EVENT = 0, 3, 6, 9, 12, 15, 18
 C_PAIRED, C_DEFICIT, C_CLAMP, C_REDRAW = 34, 35, 36, 37
+C_EICAND, C_EINULL, C_PAIRED_NEG, C_DEFICIT_NEG = 38, 39, 40, 41
 
 EXPORTS = ("pic_version", "pic_query", "pic_create", "pic_destroy", "pic_load_uniform", "pic_load_profiles",
            "pic_set_particles",

@@ -7,8 +7,8 @@ namespace picmcc {
 
 constexpr int NSP = 3;
 constexpr int MAXPROC = 16;
-constexpr int MAXPROC_SP = 8;      // processes per species
-constexpr int NCOUNT = 40;
+constexpr int MAXPROC_SP = 12;     // processes per species
+constexpr int NCOUNT = 44;
 constexpr int NBIN = 256;
 constexpr int CD_MAX = 32767;      // longest stored free flight [steps]
 constexpr int MAXPROD = 1 << 24;   // products per species per step (24-bit local index)
@@ -22,11 +22,16 @@ constexpr int W_CD_SHIFT = 16;
 constexpr int32_t W_DEAD = -1;
 
 enum { K_ELASTIC = 0, K_EXCITE = 1, K_IONIZE = 2, K_ATTACH = 3, K_CX = 4, K_NEUTRALIZE = 5, K_DETACH = 6,
-       K_ION_ELASTIC = 7 };
-enum { T_O2 = 0, T_O2A = 1, T_GRIDPOS = 2 };
-enum { P_LOAD = 1, P_CAND = 2, P_TARGET = 3, P_PROD = 4, P_PAIR = 5 };
+       K_ION_ELASTIC = 7, K_RECOMB = 8, K_EDETACH = 9 };
+enum { T_O2 = 0, T_O2A = 1, T_GRIDPOS = 2, T_GRIDNEG = 3 };
+enum { P_LOAD = 1, P_CAND = 2, P_TARGET = 3, P_PROD = 4, P_PAIR = 5, P_EION = 6 };
 enum { C_PUSH = 0, C_CAND = 3, C_NULL = 6, C_ABS0 = 9, C_ABSL = 12, C_BORN = 15, C_EVENT = 18,
-       C_PAIRED = 34, C_DEFICIT = 35, C_CLAMP = 36, C_REDRAW = 37 };
+       C_PAIRED = 34, C_DEFICIT = 35, C_CLAMP = 36, C_REDRAW = 37, C_EICAND = 38, C_EINULL = 39,
+       C_PAIRED_NEG = 40, C_DEFICIT_NEG = 41 };
+// parent-species code of the electron born in an electron-impact detachment (its
+// parent key sorts after those of the three species) and the species field of
+// the event records of the electron-ion test
+constexpr int PS_EION = 3;
 enum { E_CAPACITY = 1, E_IDOVERFLOW = 2, E_NAN = 4 };
 enum { F_EXT_FIELD = 1, F_NO_COLL = 2 };
 
@@ -41,9 +46,13 @@ struct Scalars {
   double numax_neg;                // O- bound of the current ion step [1/s]
   double pnull_neg;                // 1 - exp(-numax_neg dt_i)
   float inv_numax_neg;
-  int32_t pair_active;             // pending neutralisation partners
+  int32_t pair_active;             // pending O2+ partners (neutralisation, recombination)
   uint32_t ticket;                 // last-block-done counter
-  int32_t pad;
+  int32_t pair_active_neg;         // pending O- partners (electron-impact detachment)
+  double numax_ei;                 // electron-ion bound of the current ion step [1/s]
+  double pnull_ei;                 // 1 - exp(-numax_ei dt_i)
+  float inv_numax_ei;
+  int32_t pad3;
   unsigned long long nsort[NSP];   // slots seen by the running sort
   // current density at the driven electrode: state of the previous field solve
   double e0_prev, u_prev;
@@ -94,8 +103,9 @@ struct Sim {
   double mass[NSP];
   float vt_gas[NSP];               // sqrt(k T_gas / m_s): Maxwellian of newborn ions
   // processes
-  int32_t nproc_sp[NSP];
-  ProcDev proc[NSP][MAXPROC_SP];
+  int32_t nproc_sp[NSP];           // electrons: the channels with neutral targets only
+  ProcDev proc[NSP][MAXPROC_SP];   // electrons: then nei electron-ion channels at [0][nproc_sp[0] + q]
+  int32_t nei;
   const float *sigma;              // [nproc][ntab] FP32
   const double *hbound;            // [nproc][ntab-1] max(sigma_k, sigma_k+1) g(E_k+1), FP64
   int32_t ntab;
@@ -119,7 +129,9 @@ struct Sim {
   unsigned long long *esum, *ecnt; // [3][ng]
   unsigned long long *edf, *iedf;  // [3][NBIN], [3][2][NBIN]
   unsigned long long *nacc;        // [2] nacc, ndiag
-  int32_t *kleft;                  // [ng] neutralisations waiting for a partner
+  int32_t *kleft;                  // [ng] O2+ partners still to remove per cell
+  int32_t *kleft_neg;              // [ng] O- partners still to remove per cell
+  float *dens_ei;                  // [2][ng+1] O2+, O- node densities of the field solve [m^-3]
   unsigned long long *cmin;        // [2][ng] pairing minima
   int32_t *sortcnt, *sortbase;     // [ng], [ng]
   Scalars *sc;

@@ -117,13 +117,17 @@ __device__ __forceinline__ void log_event(const Sim &S, int64_t step, int s, uin
 
 // reserve the slot of a product of species s born from parent (ps, pid).  Its
 // parent key (ps, pid) goes to the id assignment, bucketed by its position in
-// the ordered key space [0, next_id[0]) + [0, next_id[1]) + [0, next_id[2]).
-struct IdSpace { uint64_t off[NSP]; uint64_t total; };
+// the ordered key space [0, next_id[0]) + [0, next_id[1]) + [0, next_id[2]) +
+// [0, next_id[0]) (the last segment: ps = PS_EION, electrons of an
+// electron-impact detachment, whose parent may also have ionised this step).
+struct IdSpace { uint64_t off[NSP + 1]; uint64_t total; };
 
 __device__ __forceinline__ IdSpace id_space(const Sim &S) {
   IdSpace r;
   uint64_t t = 0;
   for (int s = 0; s < NSP; ++s) { r.off[s] = t; t += S.sc->next_id[s]; }
+  r.off[PS_EION] = t;
+  t += S.sc->next_id[0];
   r.total = t > 0 ? t : 1;
   return r;
 }
@@ -1001,35 +1005,40 @@ __device__ void ionprep_block(const Sim &S) {
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ionprep(Sim S) { ionprep_block<BS>(S); }
 
-// Pairing round r of an ion step.  Every neutralised O- in cell j removes one
-// pre-step O2+ of cell j: round r removes the winner of round r-1 (smallest key
-// (pairing draw, id) among the O2+ left in the cell) and finds the next minimum.
-// The last block to finish settles the per-cell bookkeeping.
+// Pairing round r of an ion step for partners of species sp.  O2+ (sp = 1): one
+// per neutralised O- and per recombined electron of cell j; O- (sp = 2): one per
+// electron-impact detachment of cell j.  Partners are ions of cell j present
+// before the step: round r removes the winner of round r-1 (smallest key
+// (pairing draw, id) among the ions left in the cell) and finds the next
+// minimum.  The last block to finish settles the per-cell bookkeeping.
 template <int BS>
-__device__ void pair_block(const Sim &S, int64_t step, int r) {
-  if (!S.sc->pair_active) return;
+__device__ void pair_block(const Sim &S, int64_t step, int r, int sp) {
+  int32_t *active = sp == 1 ? &S.sc->pair_active : &S.sc->pair_active_neg;
+  if (!*active) return;
+  int32_t *kleft = sp == 1 ? S.kleft : S.kleft_neg;
+  const int c_paired = sp == 1 ? C_PAIRED : C_PAIRED_NEG, c_deficit = sp == 1 ? C_DEFICIT : C_DEFICIT_NEG;
   const int ng = S.ng, nn = ng + 1, R = S.pair_rounds;
   unsigned long long *cur = S.cmin + (size_t)(r & 1) * ng;
   unsigned long long *prev = S.cmin + (size_t)((r + 1) & 1) * ng;
-  const Particles &P = S.p[1];
-  const int64_t N = (int64_t)S.sc->n[1];
-  unsigned long long *Qp = S.Q + nn;
+  const Particles &P = S.p[sp];
+  const int64_t N = (int64_t)S.sc->n[sp];
+  unsigned long long *Qp = S.Q + (size_t)sp * nn;
   for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
     const int32_t w = P.w[i];
     if (w < 0) continue;
     const int c = w & (int32_t)W_CELL;
     const bool want_prev = r > 0 && prev[c] != ~0ull;
-    const bool want_cur = r < R && S.kleft[c] > 0;
+    const bool want_cur = r < R && kleft[c] > 0;
     if (!want_prev && !want_cur) continue;
     const uint32_t id = P.id[i];
-    const unsigned long long key = ((unsigned long long)draw(S, 1, id, step, P_PAIR, 0).x << 32) | id;
+    const unsigned long long key = ((unsigned long long)draw(S, sp, id, step, P_PAIR, 0).x << 32) | id;
     if (want_prev && key == prev[c]) {
       const float off = P.off[i];
       const unsigned long long a = cic_a(off);
       atomicAdd(&Qp[c], (unsigned long long)(-(long long)(4294967296ull - a)));
       atomicAdd(&Qp[c + 1], (unsigned long long)(-(long long)a));
       P.w[i] = W_DEAD;
-      atomicAdd(&S.sc->cnt[C_PAIRED], 1ull);
+      atomicAdd(&S.sc->cnt[c_paired], 1ull);
       continue;
     }
     if (want_cur) atomicMin(&cur[c], key);
@@ -1046,25 +1055,144 @@ __device__ void pair_block(const Sim &S, int64_t step, int r) {
   __syncthreads();
   for (int c = threadIdx.x; c < ng; c += BS) {
     if (r > 0) prev[c] = ~0ull;
-    const int k = S.kleft[c];
+    const int k = kleft[c];
     if (k <= 0) continue;
     if (r < R && cur[c] != ~0ull) {
-      S.kleft[c] = k - 1;
+      kleft[c] = k - 1;
       more = 1;
     } else {
-      atomicAdd(&S.sc->cnt[C_DEFICIT], (unsigned long long)k);
-      S.kleft[c] = 0;
+      atomicAdd(&S.sc->cnt[c_deficit], (unsigned long long)k);
+      kleft[c] = 0;
     }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    S.sc->pair_active = more;
+    *active = more;
     S.sc->ticket = 0u;
   }
 }
 
 template <int BS>
-__global__ __launch_bounds__(BS) void k_pair(Sim S, int64_t step, int r) { pair_block<BS>(S, step, r); }
+__global__ __launch_bounds__(BS) void k_pair(Sim S, int64_t step, int r, int sp) { pair_block<BS>(S, step, r, sp); }
+
+// Electron-ion bound of an ion step (Table 1 (16), (22)): the O2+ and O- node
+// densities of the field solve, kept before the field kernel clears the ion
+// histograms, and nu_ei = max over the table intervals of sum_q n_max,q H_q
+// (H: largest sigma g of the interval, the ion at rest).
+template <int BS>
+__global__ __launch_bounds__(BS) void k_eiprep(Sim S) {
+  __shared__ double red[BS];
+  const int ng = S.ng, nn = ng + 1;
+  double nmax[2];
+  for (int t = 0; t < 2; ++t) {
+    double m = 0.0;
+    for (int j = threadIdx.x; j < nn; j += BS) {
+      const double v = (double)S.Q[(size_t)(1 + t) * nn + j] * ((j == 0 || j == ng) ? 2.0 : 1.0) * S.wd;
+      S.dens_ei[(size_t)t * nn + j] = (float)v;
+      m = fmax(m, v);
+    }
+    red[threadIdx.x] = m;
+    __syncthreads();
+    for (int o = BS / 2; o > 0; o >>= 1) {
+      if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+      __syncthreads();
+    }
+    nmax[t] = red[0];
+    __syncthreads();
+  }
+  const int n0 = S.nproc_sp[0];
+  double best = 0.0;
+  for (int k = threadIdx.x; k < S.ntab - 1; k += BS) {
+    double sum = 0.0;
+    for (int q = 0; q < S.nei; ++q) {
+      const ProcDev &pd = S.proc[0][n0 + q];
+      sum += nmax[pd.target == T_GRIDPOS ? 0 : 1] * S.hbound[(size_t)pd.tab * (S.ntab - 1) + k];
+    }
+    best = fmax(best, sum);
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int o = BS / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double nu = red[0];
+    S.sc->numax_ei = nu;
+    S.sc->pnull_ei = 1.0 - exp(-nu * S.dti);
+    S.sc->inv_numax_ei = nu > 0.0 ? (float)(1.0 / nu) : 0.0f;
+  }
+}
+
+// Table 1 (16) e + O2+ -> O + O and (22) e + O- -> O + 2e, once per ion step after
+// the electron push: every electron present at the start of the step is a
+// candidate with probability 1 - exp(-nu_ei dt_i); the channel follows from
+// u nu_ei against the running sum of n(x) sigma(E) g, the ion at rest (g is the
+// electron speed, E its energy).  (16): the electron leaves the gap and its charge
+// the histogram; an O2+ of its cell goes to the pairing.  (22): E - E_th shared
+// as (1 - r, r) by the electron and a new one, both isotropic; an O- of the cell
+// goes to the pairing.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_eion(Sim S, int64_t step) {
+  const double pnull = S.sc->pnull_ei;
+  if (!(pnull > 0.0)) return;
+  const float inv_nu = S.sc->inv_numax_ei;
+  const Particles &P = S.p[0];
+  const int64_t N = (int64_t)S.sc->n[0];
+  const int nn = S.ng + 1, n0 = S.nproc_sp[0];
+  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
+    const int32_t w = P.w[i];
+    if (w < 0) continue;
+    const uint32_t id = P.id[i];
+    const U4 c = draw(S, 0, id, step, P_EION, 0);
+    if (!((double)unif(c.x) < pnull)) continue;
+    atomicAdd(&S.sc->cnt[C_EICAND], 1ull);
+    const int cell = w & (int32_t)W_CELL;
+    const float off = P.off[i], vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
+    const ECand en = electron_energy(S, vx * vx + vy * vy + vz * vz);
+    if (en.clamped) atomicAdd(&S.sc->cnt[C_CLAMP], 1ull);
+    const TabPos tp = tab_pos(S, en.ec);
+    const float target = unif(c.y);
+    float acc = 0.0f, eth = 0.0f;
+    int chosen = -1, kind = 0;
+    for (int q = 0; q < S.nei; ++q) {
+      const ProcDev &pd = S.proc[0][n0 + q];
+      const float *nd = S.dens_ei + (pd.target == T_GRIDPOS ? 0 : nn);
+      const float dens = fmaf(off, nd[cell + 1] - nd[cell], nd[cell]) * inv_nu;
+      const float sg = en.ec < pd.e_th ? 0.0f : tab_sigma(S.sigma + (size_t)pd.tab * S.ntab, tp);
+      acc = fmaf(dens * sg, en.g, acc);
+      if (target < acc) { chosen = pd.tab; kind = pd.kind; eth = pd.e_th; break; }
+    }
+    log_event(S, step, PS_EION, id, chosen);
+    if (chosen < 0) {
+      atomicAdd(&S.sc->cnt[C_EINULL], 1ull);
+      continue;
+    }
+    atomicAdd(&S.sc->cnt[C_EVENT + chosen], 1ull);
+    if (kind == K_RECOMB) {
+      const unsigned long long a = cic_a(off);
+      atomicAdd(&S.Q[cell], (unsigned long long)(-(long long)(4294967296ull - a)));
+      atomicAdd(&S.Q[cell + 1], (unsigned long long)(-(long long)a));
+      P.w[i] = W_DEAD;
+      atomicAdd(&S.kleft[cell], 1);
+      S.sc->pair_active = 1;
+    } else {
+      const U4 p0 = draw(S, 0, id, step, P_EION, 1);
+      const float er = fmaxf(en.e - eth, 0.0f), r = unif(p0.x);
+      float d0, d1, d2, s0, s1, s2;
+      iso_dir(c.z, c.w, d0, d1, d2);
+      const float vn = sqrtf(S.two_e_m[0] * ((1.0f - r) * er));
+      P.vx[i] = vn * d0; P.vy[i] = vn * d1; P.vz[i] = vn * d2;
+      iso_dir(p0.y, p0.z, s0, s1, s2);
+      const float vm = sqrtf(S.two_e_m[0] * (r * er));
+      emit(S, 0, PS_EION, id, cell | (int32_t)new_flight_f(S.inv_nd_ef, p0.w), off, vm * s0, vm * s1, vm * s2);
+      dep_global(S.Q, cell, off);
+      atomicAdd(&S.sc->cnt[C_BORN + 0], 1ull);
+      atomicAdd(&S.kleft_neg[cell], 1);
+      S.sc->pair_active_neg = 1;
+    }
+  }
+}
 
 // ---------------------------------------------------------------- cell sort
 // Counting sort by cell, dropping dead particles.  Each thread reads GROUP
@@ -1481,7 +1609,7 @@ __global__ __launch_bounds__(BS) void k_pair_b(const Sim *__restrict__ sims, con
                                                 uint64_t mask, int rel, int r) {
   const int m = blockIdx.y;
   if (!in_mask(mask, m) || r > sims[m].pair_rounds) return;
-  pair_block<BS>(sims[m], bd->base[m] + rel, r);
+  pair_block<BS>(sims[m], bd->base[m] + rel, r, 1);
 }
 
 template <int BS>
@@ -1608,8 +1736,18 @@ hipError_t launch_ionprep(const Sim &S, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_pair(const Sim &S, int64_t step, int r, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_pair<GBS>), dim3(grid), dim3(GBS), 0, st, S, step, r);
+hipError_t launch_pair(const Sim &S, int64_t step, int r, int sp, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_pair<GBS>), dim3(grid), dim3(GBS), 0, st, S, step, r, sp);
+  return hipGetLastError();
+}
+
+hipError_t launch_eiprep(const Sim &S, hipStream_t st) {
+  hipLaunchKernelGGL((k_eiprep<FBS>), dim3(1), dim3(FBS), 0, st, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_eion(const Sim &S, int64_t step, int grid, hipStream_t st) {
+  hipLaunchKernelGGL((k_eion<GBS>), dim3(grid), dim3(GBS), 0, st, S, step);
   return hipGetLastError();
 }
 

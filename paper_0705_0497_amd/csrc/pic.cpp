@@ -18,7 +18,9 @@ hipError_t launch_push(const Sim &S, int s, int64_t step, int grid, int block, h
 hipError_t launch_field(const Sim &S, int64_t step, int mode, hipStream_t st);
 hipError_t launch_fixup(const Sim &S, hipStream_t st);
 hipError_t launch_ionprep(const Sim &S, hipStream_t st);
-hipError_t launch_pair(const Sim &S, int64_t step, int r, int grid, hipStream_t st);
+hipError_t launch_pair(const Sim &S, int64_t step, int r, int sp, int grid, hipStream_t st);
+hipError_t launch_eiprep(const Sim &S, hipStream_t st);
+hipError_t launch_eion(const Sim &S, int64_t step, int grid, hipStream_t st);
 hipError_t launch_sort(const Sim &S, int s, const Particles &dst, int grid, hipStream_t st);
 hipError_t launch_diag(const Sim &S, int s, int grid, hipStream_t st);
 hipError_t launch_load(const Sim &S, int s, int64_t count, float vth, int grid, hipStream_t st);
@@ -59,7 +61,7 @@ struct Layout {
   size_t part[NSP][2][6];   // two buffers x (w, off, vx, vy, vz, id)
   size_t pkey[NSP], pbkt[NSP], ptmp[NSP], bcnt;
   size_t Q, E, phi, sumQ, sumphi, esum, ecnt, edf, iedf, nacc, kleft, cmin, sortcnt, sortbase, sc, sigma,
-      hbound, events, partials, ttot, blkcnt, prof, jsum, jcnt, jpow;
+      hbound, events, partials, ttot, blkcnt, prof, jsum, jcnt, jpow, kleft_neg, dens_ei;
   size_t take(size_t bytes) {
     const size_t o = total;
     total += (bytes + 255) & ~(size_t)255;
@@ -104,6 +106,8 @@ Layout make_layout(const pic_config &c, const pic_species *sp, int nproc) {
   L.jsum = L.take(8 * (size_t)c.steps_per_cycle);   // current density per rf phase
   L.jcnt = L.take(8 * (size_t)c.steps_per_cycle);
   L.jpow = L.take(16);
+  L.kleft_neg = L.take(4 * (size_t)c.ng);          // O- partners of electron-impact detachment
+  L.dens_ei = L.take(4 * 2 * nn);                   // ion node densities for the electron-ion test
   return L;
 }
 
@@ -149,19 +153,24 @@ int validate(const pic_config *c, const pic_species *sp, const pic_process *pr, 
   for (int p = 0; p < nproc; ++p) {
     const pic_process &P = pr[p];
     if (P.species < 0 || P.species >= NSP) { msg = "process species out of range"; return PIC_EINVAL; }
-    const bool ok = (P.species == 0 && P.kind >= PIC_ELASTIC && P.kind <= PIC_ATTACH) ||
+    const bool ok = (P.species == 0 && ((P.kind >= PIC_ELASTIC && P.kind <= PIC_ATTACH) ||
+                                        P.kind == PIC_RECOMB || P.kind == PIC_EDETACH)) ||
                     (P.species == 1 && (P.kind == PIC_CX || P.kind == PIC_ION_ELASTIC)) ||
                     (P.species == 2 && (P.kind == PIC_NEUTRALIZE || P.kind == PIC_DETACH || P.kind == PIC_ION_ELASTIC));
     if (!ok) { msg = "process kind not valid for its species"; return PIC_EINVAL; }
-    if (P.target < PIC_T_O2 || P.target > PIC_T_GRIDPOS || ((P.target == PIC_T_GRIDPOS) != (P.kind == PIC_NEUTRALIZE))) {
-      msg = "process target invalid (the O2+ grid density is the partner of neutralisation only)"; return PIC_EINVAL;
+    const bool gridpos = P.kind == PIC_NEUTRALIZE || P.kind == PIC_RECOMB, gridneg = P.kind == PIC_EDETACH;
+    if (P.target < PIC_T_O2 || P.target > PIC_T_GRIDNEG || ((P.target == PIC_T_GRIDPOS) != gridpos) ||
+        ((P.target == PIC_T_GRIDNEG) != gridneg)) {
+      msg = "process target invalid (grid densities: O2+ for neutralisation and recombination, O- for "
+            "electron-impact detachment, and only there)";
+      return PIC_EINVAL;
     }
     if (!(std::isfinite(P.e_th) && P.e_th >= 0.0) || !finite_pos(P.target_mass) || !P.sigma) {
       msg = "process needs e_th >= 0, target_mass > 0 and a table"; return PIC_EINVAL;
     }
     for (int k = 0; k < c->table_n; ++k)
       if (!(std::isfinite(P.sigma[k]) && P.sigma[k] >= 0.0)) { msg = "cross sections must be finite and >= 0"; return PIC_EINVAL; }
-    if (++per[P.species] > MAXPROC_SP) { msg = "at most 8 processes per species"; return PIC_EINVAL; }
+    if (++per[P.species] > MAXPROC_SP) { msg = "at most 12 processes per species"; return PIC_EINVAL; }
   }
   return PIC_OK;
 }
@@ -374,10 +383,18 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
   S.nd_e = h->numax[0] * dt;
   S.inv_nd_ef = S.nd_e > 0.0 ? (float)(1.0 / S.nd_e) : 0.0f;
   S.pnull_pos = 1.0 - std::exp(-h->numax[1] * dti);
-  for (int p = 0; p < nproc; ++p) {
+  // electrons: the channels with neutral targets first (free flights, push), then
+  // the electron-ion channels (the ion-step test)
+  int order[MAXPROC], no = 0;
+  for (int pass = 0; pass < 2; ++pass)
+    for (int p = 0; p < nproc; ++p)
+      if ((h->pr[p].kind == PIC_RECOMB || h->pr[p].kind == PIC_EDETACH) == (pass == 1)) order[no++] = p;
+  for (int q = 0; q < nproc; ++q) {
+    const int p = order[q];
     const pic_process &P = h->pr[p];
     const int s = P.species;
-    ProcDev &d = S.proc[s][S.nproc_sp[s]++];
+    const bool eion = P.kind == PIC_RECOMB || P.kind == PIC_EDETACH;
+    ProcDev &d = eion ? S.proc[0][S.nproc_sp[0] + S.nei++] : S.proc[s][S.nproc_sp[s]++];
     const double mu = reduced_mass(h, P);
     d.kind = P.kind; d.target = P.target; d.tab = p;
     d.e_th = (float)P.e_th;
@@ -401,6 +418,8 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
   S.iedf = (unsigned long long *)(ws + L.iedf);
   S.nacc = (unsigned long long *)(ws + L.nacc);
   S.kleft = (int32_t *)(ws + L.kleft);
+  S.kleft_neg = (int32_t *)(ws + L.kleft_neg);
+  S.dens_ei = (float *)(ws + L.dens_ei);
   S.cmin = (unsigned long long *)(ws + L.cmin);
   S.sortcnt = (int32_t *)(ws + L.sortcnt);
   S.bcnt = (int32_t *)(ws + L.bcnt);
@@ -751,6 +770,9 @@ static int enqueue_step(pic_handle *h, hipEvent_t ev0, hipEvent_t ev1) {
   Sim &S = h->S;
   const pic_config &c = h->cfg;
   const int64_t n = h->step;
+  // electron-ion channels: the ion densities of this step's field, before it clears them
+  const bool eion = S.nei > 0 && !(S.flags & F_NO_COLL) && n % c.ksub == 0;
+  if (eion) HIPCHK(h, launch_eiprep(S, h->stream));
   HIPCHK(h, launch_field(S, n, 0, h->stream));
   if (c.diag_every > 0 && n % c.diag_every == 0)
     for (int s = 0; s < NSP; ++s) HIPCHK(h, launch_diag(S, s, h->hgrid, h->stream));
@@ -767,13 +789,16 @@ static int enqueue_step(pic_handle *h, hipEvent_t ev0, hipEvent_t ev1) {
   HIPCHK(h, launch_push(S, 0, n, h->grid[0], h->block, h->stream));
   if (ev1) HIPCHK(h, hipEventRecord(ev1, h->stream));
   HIPCHK(h, launch_reduce(S, 0, h->grid[0], h->stream));
+  if (eion) HIPCHK(h, launch_eion(S, n, h->hgrid, h->stream));
   if (n % c.ksub == 0) {
     HIPCHK(h, launch_push(S, 1, n, h->grid[1], h->block, h->stream));
     HIPCHK(h, launch_reduce(S, 1, h->grid[1], h->stream));
     HIPCHK(h, launch_ionprep(S, h->stream));
     HIPCHK(h, launch_push(S, 2, n, h->grid[2], h->block, h->stream));
     HIPCHK(h, launch_reduce(S, 2, h->grid[2], h->stream));
-    for (int r = 0; r <= c.pair_rounds; ++r) HIPCHK(h, launch_pair(S, n, r, h->pgrid, h->stream));
+    for (int r = 0; r <= c.pair_rounds; ++r) HIPCHK(h, launch_pair(S, n, r, 1, h->pgrid, h->stream));
+    if (eion)
+      for (int r = 0; r <= c.pair_rounds; ++r) HIPCHK(h, launch_pair(S, n, r, 2, h->pgrid, h->stream));
   }
   h->step = n + 1;
   return PIC_OK;
@@ -1123,6 +1148,8 @@ int pic_batch_create(pic_handle *const *members, int32_t n, const pic_batch_conf
       if (members[k] == h) return bfail(nullptr, PIC_EINVAL, who + "listed twice");
     if (h->batch_busy) return bfail(nullptr, PIC_EBUSY, who + "busy in another batch");
     if (h->stream != (hipStream_t)stream) return bfail(nullptr, PIC_EINVAL, who + "created on another stream");
+    if (h->S.nei > 0)
+      return bfail(nullptr, PIC_EINVAL, who + "has electron-ion channels, which only single discharges run");
     const pic_config &c = h->cfg;
     if (c.steps_per_cycle != spc) return bfail(nullptr, PIC_EINVAL, who + "steps_per_cycle differs");
     if (spc % c.ksub != 0) return bfail(nullptr, PIC_EINVAL, who + "ksub must divide steps_per_cycle");

@@ -58,9 +58,11 @@ def xi_of(st):
 
 
 def band_ids(oracle_events):
-    """(species, id) pairs whose decision fell within the 1e-6 band."""
+    """(species, id) pairs whose decision fell within the 1e-6 band; an electron-ion
+    test in the band (species 3) marks the electron (species 0) as well."""
     ev = oracle_events
-    return set(map(tuple, ev[ev[:, 4] != 0][:, [1, 2]].tolist()))
+    out = set(map(tuple, ev[ev[:, 4] != 0][:, [1, 2]].tolist()))
+    return out | {(0, i) for s, i in out if s == 3}
 
 
 def compare_events(gpu_ev, orc_ev):

@@ -78,6 +78,23 @@ def test_query_rejects_bad_species_and_processes():
         B.pic_query(cfg, sp, pr, n)
 
 
+def test_query_accepts_all_sixteen_channels_and_checks_electron_ion_targets():
+    full = I.make_processes_full()
+    cfg, sp, pr, n, tabs = _args(procs=full)
+    assert n == 16 and B.pic_query(cfg, sp, pr, n) > 0
+    names = [p.name for p in full]
+    for name, bad in (("e-recomb", "grid-"), ("e-edet", "grid+"), ("e-recomb", "O2"), ("O--neut", "grid-")):
+        cfg, sp, pr, n, tabs = _args(procs=full)
+        pr[names.index(name)].target = B.TARGET[bad]
+        with pytest.raises(B.PicError) as e:
+            B.pic_query(cfg, sp, pr, n)
+        assert e.value.code == B.PIC_EINVAL, (name, bad)
+    cfg, sp, pr, n, tabs = _args(procs=full)
+    pr[names.index("O2+-cx")].kind = B.KIND["recomb"]      # electron-ion kinds belong to electrons
+    with pytest.raises(B.PicError):
+        B.pic_query(cfg, sp, pr, n)
+
+
 def test_binding_fails_loudly_without_library(monkeypatch):
     monkeypatch.setattr(B, "_lib", None)
     monkeypatch.setattr(B, "LIB_PATH", "/nonexistent/libpicmcc.so")

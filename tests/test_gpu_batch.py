@@ -150,6 +150,10 @@ def test_batch_validation_and_busy_members():
         B.Batch([mem[0], bad])
     with pytest.raises(B.PicError):
         B.Batch([mem[0], mem[0]])
+    eion = B.Discharge(ds[1], I.make_processes_full(), stream=stream)   # electron-ion channels: single runs only
+    with pytest.raises(B.PicError) as e:
+        B.Batch([mem[0], eion])
+    assert e.value.code == B.PIC_EINVAL
     with pytest.raises(B.PicError):
         B.Batch(mem, sort_every=7)                           # does not divide the cycle
     b = B.Batch(mem, sort_every=20)

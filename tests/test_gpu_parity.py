@@ -407,3 +407,42 @@ def test_extended_channels_single_step_element_by_element(step0):
         np.testing.assert_array_equal(g.hist()[s], po.deposit_canonical(d.ng, gs["cell"], gs["off"]))
     if not band:
         np.testing.assert_array_equal(g.counters()[:po.C_CLAMP], o.counters()[:po.C_CLAMP])
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("step0", [0, 20])
+def test_electron_ion_channels_single_step_element_by_element(step0):
+    # all sixteen channels; Table 1 (16) and (22) with sigma ~ E^-1/2 large enough that one ion
+    # step holds several of each, and the pairing removes their partners
+    d = I.config(1)
+    procs = H.neutralising(I.make_processes_full())
+    for k, p in enumerate(procs):
+        if p.name == "e-recomb":
+            procs[k] = I.Process("e-recomb", 0, "recomb", "grid+", 0.0, I.M_O2PLUS,
+                                 I.power_law_table(1e-13, 0.0, 0.5, 0.0), {})
+        if p.name == "e-edet":
+            procs[k] = I.Process("e-edet", 0, "edetach", "grid-", 1.461, I.M_OMINUS,
+                                 I.power_law_table(1e-14, 0.0, 0.5, 1.461), {})
+    o, g, st = _pair(d, procs, step0, seed_steps=30)
+    o.log_events(True)
+    o.step(1)
+    g.step(1)
+    gev = g.events()
+    oev = o.events()
+    names = [p.name for p in procs]
+    ei = oev[oev[:, 1] == 3]
+    for nm in ("e-recomb", "e-edet"):
+        assert np.sum(ei[:, 3] == names.index(nm)) >= 3, nm
+    assert np.sum(ei[:, 3] == -1) >= 3                      # null collisions of the test
+    bad, band = H.compare_events(gev, oev)
+    assert not bad, f"decisions differ outside the band: {bad[:10]}"
+    for s in range(3):
+        gs, nid_g = g.get_particles(s)
+        dx, dv = H.compare_states(gs, o.get_particles(s), d.species()[s], skip=band, s=s)
+        assert dx <= H.POS_TOL and dv <= H.VEL_TOL, (s, dx, dv)
+        np.testing.assert_array_equal(g.hist()[s], po.deposit_canonical(d.ng, gs["cell"], gs["off"]))
+    if not band:
+        gc, oc = g.counters(), o.counters()
+        np.testing.assert_array_equal(gc[:po.C_CLAMP], oc[:po.C_CLAMP])
+        np.testing.assert_array_equal(gc[po.C_EICAND:po.C_DEFICIT_NEG + 1], oc[po.C_EICAND:po.C_DEFICIT_NEG + 1])
+        assert all(g.count(s) == o.count(s) for s in range(3))
