@@ -170,6 +170,42 @@ def eq1_sigma0_m2() -> float:
     return 5.96e-16 * 1e-4
 
 
+# ---- the paper's cross-section models as table generators (section 2) --------
+BOHR_M = 5.29177210903e-11          # Bohr radius [m]
+HARTREE_EV = 27.211386245988        # Hartree energy [eV]
+
+
+def landau_zener(e, r_x):
+    """Two-channel Landau-Zener cross section of ion-ion neutralisation,
+    sigma_n = 4 pi R_x^2 (1 + 1 / (R_x E)), read in atomic units: R_x in Bohr
+    radii, E the relative energy in Hartree, sigma in Bohr^2 (1 / R_x is the
+    Coulomb energy at the crossing radius).  E in eV, result in m^2."""
+    e = np.asarray(e, dtype=np.float64)
+    return 4.0 * math.pi * (r_x * BOHR_M) ** 2 * (1.0 + HARTREE_EV / (r_x * e))
+
+
+def landau_zener_table(r_x) -> np.ndarray:
+    """landau_zener on the TABLE_N-point grid."""
+    return landau_zener(energy_grid(), r_x)
+
+
+def cx_from_momentum_transfer(sigma_m, e_lo=0.251, e_hi=8.5) -> np.ndarray:
+    """(O2+, O2) charge exchange from a momentum-transfer cross section sigma_m
+    (callable of E [eV] -> m^2, or an array on the table grid): sigma_cx = sigma_m / 2
+    below e_lo and above e_hi, linear in E in between."""
+    e = energy_grid()
+    sm = np.asarray(sigma_m(e) if callable(sigma_m) else sigma_m, dtype=np.float64)
+    if sm.shape != e.shape:
+        raise ValueError("sigma_m must be given on the table grid")
+    f = (lambda x: 0.5 * np.asarray(sigma_m(x), dtype=np.float64)) if callable(sigma_m) else \
+        (lambda x: 0.5 * np.interp(np.log(x), np.log(e), sm))
+    lo, hi = float(f(np.array([e_lo]))[0]), float(f(np.array([e_hi]))[0])
+    out = 0.5 * sm
+    mid = (e > e_lo) & (e < e_hi)
+    out[mid] = lo + (hi - lo) * (e[mid] - e_lo) / (e_hi - e_lo)
+    return out
+
+
 # Windows of the synthetic parameters.  Generic orders of magnitude chosen so
 # that the seeded discharge is sustained; not fitted to any measured data.
 _WINDOWS = {
