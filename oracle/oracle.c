@@ -61,6 +61,12 @@ struct orc_sim {
   int32_t jvalid;              /* e0_prev, u_prev, abs0_prev hold the previous field solve */
   double e0_prev, u_prev;
   int64_t abs0_prev[ORC_NSP];
+  /* spatially resolved O2(a1Delta_g) (section 4's proposed extension) */
+  int32_t meta_on, meta_proc;
+  double meta_D, meta_nuq, meta_h;
+  int64_t *meta_src;           /* CIC tally of the source events, 2^-32 units per node */
+  double *na;                  /* O2(a) density at the nodes [m^-3] */
+  int64_t meta_step0;          /* step of the last update */
 };
 
 /* ------------------------------------------------------------------ */
@@ -158,7 +164,12 @@ static double node_density(const orc_sim *S, int s, int j) {
 static double target_density(const orc_sim *S, int p, double xi) {
   switch (S->pr[p].target) {
     case ORC_T_O2: return S->n_o2;
-    case ORC_T_O2A: return S->c.c_meta * S->n_o2;
+    case ORC_T_O2A: {
+      if (!S->meta_on) return S->c.c_meta * S->n_o2;
+      int j = (int)floor(xi);
+      double w = xi - j;
+      return (1.0 - w) * S->na[j] + w * S->na[j + 1];
+    }
     default: {
       int s = S->pr[p].target == ORC_T_GRIDPOS ? ORC_POS : ORC_NEG;
       int j = (int)floor(xi);
@@ -262,6 +273,8 @@ orc_sim *orc_create(const orc_config *cfg, const orc_species *sp, int32_t nproc,
   S->iedf = calloc((size_t)ORC_NSP * 2 * ORC_NBIN, sizeof(int64_t));
   S->kcell = calloc(cfg->ng, sizeof(int64_t));
   S->kneg = calloc(cfg->ng, sizeof(int64_t));
+  S->meta_src = calloc(nn, sizeof(int64_t));
+  S->na = calloc(nn, sizeof(double));
   S->jsum = calloc(cfg->steps_per_cycle, sizeof(double));
   S->jcnt = calloc(cfg->steps_per_cycle, sizeof(int64_t));
   S->numax[ORC_E] = nu_bound(S, ORC_E, NULL, 0);
@@ -279,7 +292,7 @@ void orc_destroy(orc_sim *S) {
   }
   free(S->sigma); free(S->Q); free(S->phi); free(S->E); free(S->sumQ); free(S->sumphi);
   free(S->esum); free(S->ecnt); free(S->edf); free(S->iedf); free(S->kcell); free(S->kneg); free(S->ev);
-  free(S->jsum); free(S->jcnt);
+  free(S->jsum); free(S->jcnt); free(S->meta_src); free(S->na);
   free(S);
 }
 
@@ -622,6 +635,7 @@ static void collide_electron(orc_sim *S, int64_t i) {
   log_event(S, ORC_E, id, chosen, band, 0);
   if (chosen < 0) { S->cnt[ORC_C_NULL + ORC_E]++; return; }
   S->cnt[ORC_C_EVENT + chosen]++;
+  if (S->meta_on && chosen == S->meta_proc) deposit_one(S->meta_src, a->xi[i]);   /* O2(a) born here */
   const orc_process *P = &S->pr[chosen];
   double d[3], vmag = sqrt(v2);
   iso_dir(c[2], c[3], d);
@@ -962,8 +976,11 @@ static void one_step(orc_sim *S) {
       if (nj > nmax) nmax = nj;
     }
     double nover[MAXPROC];
+    double namax = 0.0;
+    for (int j = 0; S->meta_on && j < nn; ++j) namax = fmax(namax, S->na[j]);
     for (int p = 0; p < S->np; ++p)
-      nover[p] = S->pr[p].target == ORC_T_GRIDPOS ? nmax : target_density(S, p, 0.0);
+      nover[p] = S->pr[p].target == ORC_T_GRIDPOS ? nmax
+               : (S->pr[p].target == ORC_T_O2A && S->meta_on) ? namax : target_density(S, p, 0.0);
     S->numax[ORC_NEG] = nu_bound(S, ORC_NEG, nover, 0);
     push_species(S, ORC_NEG, nstart[ORC_NEG]);
     pairing(S, ORC_POS, nstart[ORC_POS], S->kcell, ORC_C_PAIRED, ORC_C_DEFICIT);
@@ -1037,6 +1054,82 @@ int64_t orc_get_moments(const orc_sim *S, double *sumQ, double *sumphi, int64_t 
   if (iedf) memcpy(iedf, S->iedf, sizeof(int64_t) * ORC_NSP * 2 * ORC_NBIN);
   if (ndiag) *ndiag = S->ndiag;
   return S->nacc;
+}
+
+/* ------------------------------------------------------------------ */
+/* Spatially resolved O2(a1Delta_g), the extension section 4 proposes for the
+   uniform n = C n(O2) of Eq. (1).  Steady state of
+       D n'' - nu_q n + P(x) = 0,  0 < x < L,
+   with the surface loss of the electrodes, flux gamma v / (2 (2 - gamma)) n
+   (v the mean speed of the molecule), and P the production by the electron
+   channel meta_proc (Table 1 (14)) tallied since the last update.  Finite
+   volumes on the nodes (half volumes at the electrodes), FP64, tridiagonal. */
+int orc_metastable_config(orc_sim *S, int32_t proc, double D, double nu_q, double gamma) {
+  if (proc < 0 || proc >= S->np || S->pr[proc].species != ORC_E || S->pr[proc].kind != ORC_EXCITE) return -1;
+  if (!(D > 0.0) || !(nu_q >= 0.0) || !(gamma >= 0.0 && gamma <= 1.0) || (gamma == 0.0 && nu_q == 0.0)) return -1;
+  double M = S->pr[proc].target_mass;
+  double vbar = sqrt(8.0 * K_B * S->c.t_gas / (0.5 * TWO_PI * M));   /* mean molecular speed */
+  S->meta_on = 1;
+  S->meta_proc = proc;
+  S->meta_D = D;
+  S->meta_nuq = nu_q;
+  S->meta_h = gamma * vbar / (2.0 * (2.0 - gamma));
+  int nn = S->c.ng + 1;
+  for (int j = 0; j < nn; ++j) { S->na[j] = S->c.c_meta * S->n_o2; S->meta_src[j] = 0; }
+  S->meta_step0 = S->step;
+  return 0;
+}
+
+/* tridiagonal solve a_j x_{j-1} + b_j x_j + c_j x_{j+1} = r_j (Thomas) */
+static void thomas(int n, const double *a, const double *b, const double *c, const double *r, double *x) {
+  double *cp = malloc(sizeof(double) * n), *rp = malloc(sizeof(double) * n);
+  cp[0] = c[0] / b[0];
+  rp[0] = r[0] / b[0];
+  for (int j = 1; j < n; ++j) {
+    double m = b[j] - a[j] * cp[j - 1];
+    cp[j] = c[j] / m;
+    rp[j] = (r[j] - a[j] * rp[j - 1]) / m;
+  }
+  x[n - 1] = rp[n - 1];
+  for (int j = n - 2; j >= 0; --j) x[j] = rp[j] - cp[j] * x[j + 1];
+  free(cp); free(rp);
+}
+
+/* the steady profile for a production rate given per node [m^-3 s^-1] */
+void orc_metastable_solve(int32_t ng, double dx, double D, double nu_q, double h, const double *prod, double *n) {
+  int nn = ng + 1;
+  double *a = calloc(nn, sizeof(double)), *b = calloc(nn, sizeof(double)), *c = calloc(nn, sizeof(double));
+  double k = D / (dx * dx);
+  for (int j = 1; j < ng; ++j) { a[j] = k; b[j] = -2.0 * k - nu_q; c[j] = k; }
+  /* electrode nodes own half a cell: (D (n1 - n0) / dx - h n0) / (dx / 2) - nu_q n0 + P0 = 0 */
+  b[0] = -2.0 * k - 2.0 * h / dx - nu_q; c[0] = 2.0 * k;
+  a[ng] = 2.0 * k; b[ng] = -2.0 * k - 2.0 * h / dx - nu_q;
+  double *r = malloc(sizeof(double) * nn);
+  for (int j = 0; j < nn; ++j) r[j] = -prod[j];
+  thomas(nn, a, b, c, r, n);
+  free(a); free(b); free(c); free(r);
+}
+
+int orc_metastable_update(orc_sim *S, double *n_out) {
+  if (!S->meta_on) return -1;
+  int ng = S->c.ng, nn = ng + 1;
+  double tau = (double)(S->step - S->meta_step0) * S->dt;
+  if (!(tau > 0.0)) return -1;
+  double *prod = malloc(sizeof(double) * nn);
+  for (int j = 0; j < nn; ++j) {
+    double vol = (j == 0 || j == ng) ? 0.5 * S->dx : S->dx;
+    prod[j] = S->c.weight * ((double)S->meta_src[j] / TWO32) / (vol * tau);
+    S->meta_src[j] = 0;
+  }
+  orc_metastable_solve(ng, S->dx, S->meta_D, S->meta_nuq, S->meta_h, prod, S->na);
+  free(prod);
+  S->meta_step0 = S->step;
+  if (n_out) memcpy(n_out, S->na, sizeof(double) * nn);
+  return 0;
+}
+
+void orc_metastable_tally(const orc_sim *S, int64_t *src) {
+  memcpy(src, S->meta_src, sizeof(int64_t) * (S->c.ng + 1));
 }
 
 void orc_log_events(orc_sim *S, int32_t on) { S->logon = on; S->nev = 0; }

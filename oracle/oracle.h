@@ -145,6 +145,17 @@ int64_t orc_get_moments(const orc_sim *S, double *sumQ, double *sumphi, int64_t 
    samples; cleared with the other moments */
 void orc_get_current(const orc_sim *S, double *jsum, int64_t *jcnt, double *psum, int64_t *pn);
 
+/* spatially resolved O2(a1Delta_g) (section 4): production by the electron
+   channel proc (an excitation, Table 1 (14)), diffusion D [m^2/s], volume loss
+   nu_q [1/s], surface loss probability gamma at both electrodes.  Config starts
+   from n = C n(O2) and clears the tally; update solves the steady profile from
+   the events tallied since the last update and uses it for Eq. (1) detachment
+   from then on.  Both return 0, or -1 for invalid arguments. */
+int orc_metastable_config(orc_sim *S, int32_t proc, double D, double nu_q, double gamma);
+int orc_metastable_update(orc_sim *S, double *n_out);
+void orc_metastable_tally(const orc_sim *S, int64_t *src);
+void orc_metastable_solve(int32_t ng, double dx, double D, double nu_q, double h, const double *prod, double *n);
+
 /* event log: records of 6 int64 {step, species, id, code, band, aux};
    code >= 0 process index, -1 null, -2 capped redraw, -3 absorbed, -4 candidate
    test in the band; species ORC_EV_EION for the electron-ion test of an electron */

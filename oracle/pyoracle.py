@@ -106,12 +106,26 @@ def lib():
         L.orc_philox4x32_10.argtypes = [vp, vp, vp]
         L.orc_poisson.argtypes = [i32, dbl, dbl, vp, vp, vp]
         L.orc_deposit_canonical.argtypes = [i32, i64, vp, vp, vp]
+        L.orc_metastable_config.restype = i32
+        L.orc_metastable_config.argtypes = [vp, i32, dbl, dbl, dbl]
+        L.orc_metastable_update.restype = i32
+        L.orc_metastable_update.argtypes = [vp, vp]
+        L.orc_metastable_tally.argtypes = [vp, vp]
+        L.orc_metastable_solve.argtypes = [i32, dbl, dbl, dbl, dbl, vp, vp]
         _lib = L
     return _lib
 
 
 def _p(a):
     return a.ctypes.data_as(C.c_void_p) if a is not None else None
+
+
+def metastable_solve(ng, dx, D, nu_q, h, prod):
+    """Steady O2(a) profile on the nodes for a production rate per node [m^-3 s^-1]."""
+    prod = np.ascontiguousarray(prod, dtype=np.float64)
+    n = np.zeros(ng + 1)
+    lib().orc_metastable_solve(int(ng), float(dx), float(D), float(nu_q), float(h), _p(prod), _p(n))
+    return n
 
 
 def philox(ctr, key):
@@ -292,6 +306,23 @@ class Oracle:
         pn = np.zeros(1, dtype=np.int64)
         lib().orc_get_current(self.h, _p(js), _p(jc), _p(ps), _p(pn))
         return {"jsum": js, "jcnt": jc, "psum": float(ps[0]), "pn": int(pn[0])}
+
+    def metastable_config(self, proc, D, nu_q, gamma):
+        """Spatially resolved O2(a): production by process index proc, diffusion D
+        [m^2/s], volume loss nu_q [1/s], surface loss probability gamma."""
+        if lib().orc_metastable_config(self.h, int(proc), float(D), float(nu_q), float(gamma)) != 0:
+            raise ValueError("invalid metastable configuration")
+
+    def metastable_update(self):
+        n = np.zeros(self.ng + 1)
+        if lib().orc_metastable_update(self.h, _p(n)) != 0:
+            raise ValueError("metastable update without configuration or tally window")
+        return n
+
+    def metastable_tally(self):
+        q = np.zeros(self.ng + 1, dtype=np.int64)
+        lib().orc_metastable_tally(self.h, _p(q))
+        return q
 
     def log_events(self, on=True):
         lib().orc_log_events(self.h, 1 if on else 0)

@@ -850,3 +850,122 @@ def test_recombination_removes_a_partner_from_the_electrons_cell():
     n5 = int(np.sum(cells == 5))
     assert n5 > d.pair_rounds and c[po.C_PAIRED] == d.pair_rounds
     assert o.count(1) == 64 * 64 - d.pair_rounds
+
+
+# ---------------------------------------------------------------- spatially resolved O2(a) (section 4)
+def test_metastable_solver_closed_forms():
+    """Steady D n'' - nu n + P = 0 with the surface flux h n at both electrodes:
+    uniform P and nu = 0 give n = P x (L - x) / (2 D) + P L / (2 h) (reproduced exactly
+    by the finite volumes); h = 0 gives n = P / nu; both losses give the cosh profile."""
+    ng, L, D, h, P = 64, 0.025, 0.15, 0.1, 1e22
+    dx = L / ng
+    x = np.arange(ng + 1) * dx
+    n = po.metastable_solve(ng, dx, D, 0.0, h, np.full(ng + 1, P))
+    np.testing.assert_allclose(n, P * x * (L - x) / (2 * D) + P * L / (2 * h), rtol=1e-12)
+    n = po.metastable_solve(ng, dx, D, 50.0, 0.0, np.full(ng + 1, P))
+    np.testing.assert_allclose(n, P / 50.0, rtol=1e-12)
+    ng = 1024
+    dx = L / ng
+    x = np.arange(ng + 1) * dx
+    nu = 4e3
+    k = math.sqrt(nu / D)
+    n = po.metastable_solve(ng, dx, D, nu, h, np.full(ng + 1, P))
+    # n = P/nu (1 - A cosh(k (x - L/2))), D n'(0) = h n(0)
+    A = h / (D * k * math.sinh(k * L / 2) + h * math.cosh(k * L / 2))
+    np.testing.assert_allclose(n, P / nu * (1 - A * np.cosh(k * (x - L / 2))), rtol=1e-5)
+
+
+def _metastable_beam(n=40000, sig=3e-19, e_ev=5.0, ng=64):
+    a1 = I.constant_process("a1", 0, "excite", "O2", sig, e_th=0.977)
+    procs = [a1]
+    d = I.config(1, L=0.025, ng=ng, p=20.0, diag_every=0, counts=(n, 1, 1))
+    o = po.Oracle(d, species(n), procs, flags=po.F_EXT_FIELD, e_ext=(0.0, 0.0))
+    rng = np.random.default_rng(21)
+    v = math.sqrt(2 * e_ev * QE / ME)
+    put(o, 0, rng.uniform(0, ng, n), np.zeros(n), vy=np.full(n, v),
+        cd=rng.geometric(1 - math.exp(-o.info()["nu_max"][0] * d.dt), n).astype(np.int32))
+    empty(o, 1), empty(o, 2)
+    o.prepare(False)
+    return d, o
+
+
+def test_metastable_tally_is_the_deposit_of_the_source_events():
+    d, o = _metastable_beam()
+    o.metastable_config(0, 0.15, 0.0, 1e-3)
+    o.log_events(True)
+    o.step(1)
+    ev = o.events()
+    hit = ev[(ev[:, 1] == 0) & (ev[:, 3] == 0)][:, 2]
+    assert len(hit) > 100
+    st = o.get_particles(0)
+    sel = np.isin(st["id"], hit)
+    q = o.metastable_tally()
+    # the fixed-point linear weighting of the charge deposit at the event positions
+    xi = st["xi"][sel]
+    j = np.floor(xi).astype(np.int64)
+    a = np.rint((xi - j) * TWO32).astype(np.int64)
+    expect = np.zeros(d.ng + 1, np.int64)
+    np.add.at(expect, j, TWO32 - a)
+    np.add.at(expect, j + 1, a)
+    np.testing.assert_array_equal(q, expect)
+    assert q.sum() == len(hit) * TWO32
+
+
+def test_metastable_update_balances_production_and_losses():
+    """Summed over the finite volumes, production equals the surface loss at both
+    electrodes plus the volume loss; the production is the events' w per m^2 over
+    the tally window."""
+    d, o = _metastable_beam()
+    D, nu, gamma = 0.15, 30.0, 2e-3
+    o.metastable_config(0, D, nu, gamma)
+    steps = 40
+    o.step(steps)
+    events = o.counters()[po.C_EVENT + 0]
+    n = o.metastable_update()
+    dx = d.L / d.ng
+    vol = np.full(d.ng + 1, dx)
+    vol[0] = vol[-1] = dx / 2
+    vbar = math.sqrt(8 * KB * 300.0 / (math.pi * I.M_O2))
+    h = gamma * vbar / (2 * (2 - gamma))
+    production = d.weight * events / (steps * d.dt)
+    loss = h * (n[0] + n[-1]) + nu * float(np.sum(vol * n))
+    assert abs(loss / production - 1) < 1e-10
+    assert np.all(n > 0) and n[d.ng // 2] > n[0]          # peaked inside, lost at the walls
+    assert np.all(o.metastable_tally() == 0)
+
+
+def test_associative_detachment_follows_the_resolved_density():
+    """Eq. (1) with n(O2(a)) from the solved profile: the detachment probability per
+    ion step at position x is 1 - exp(-n_a(x) sigma g dt_i) (sigma g constant)."""
+    ad = I.Process("ad", 2, "detach", "O2a", 0.0, I.M_O2, I.power_law_table(I.eq1_sigma0_m2(), 0.0, 0.5, 0.0), {})
+    a1 = I.constant_process("a1", 0, "excite", "O2", 1e-18, e_th=0.977)
+    ng = 64
+    # the weight sets the production, hence n_a: n_a sigma g dt_i ~ 1e-2 at the centre keeps the
+    # one test per ion step at first order (bias below a third of the statistical error)
+    d = I.config(1, L=0.025, ng=ng, p=20.0, diag_every=0, counts=(20000, 1000, 200000), c_meta=0.0)
+    o = po.Oracle(d, species(20000, 0, 200000), [a1, ad], flags=po.F_EXT_FIELD, e_ext=(0.0, 0.0))
+    rng = np.random.default_rng(5)
+    v = math.sqrt(2 * 5.0 * QE / ME)
+    put(o, 0, rng.uniform(20, 44, 20000), np.zeros(20000), vy=np.full(20000, v))   # electrons in the middle
+    empty(o, 1)
+    # O- at rest in two groups: next to an electrode and at the centre
+    put(o, 2, np.concatenate([np.full(100000, 1.5), np.full(100000, 32.5)]), np.zeros(200000))
+    o.prepare(False)
+    o.metastable_config(0, 0.05, 0.0, 0.5)
+    o.set_step(1)                        # not an ion step: the O- stay untested while the tally fills
+    o.step(d.ksub - 1)
+    n_a = o.metastable_update()
+    assert n_a[32] > 3 * n_a[1]
+    mu = I.M_OMINUS * I.M_O2 / (I.M_OMINUS + I.M_O2)
+    sg = I.eq1_sigma0_m2() * math.sqrt(2 * QE / mu)
+    T = d.ksub * d.dt
+    assert 3e-3 < n_a.max() * sg * T < 2e-2
+    c0 = o.counters()
+    o.step(1)                            # the ion step
+    k = o.counters()[po.C_EVENT + 1] - c0[po.C_EVENT + 1]
+    left = o.get_particles(2)
+    gone_edge = 100000 - int(np.sum(np.floor(left["xi"]) == 1))
+    gone_mid = 100000 - int(np.sum(np.floor(left["xi"]) == 32))
+    for gone, nx in ((gone_edge, 0.5 * (n_a[1] + n_a[2])), (gone_mid, 0.5 * (n_a[32] + n_a[33]))):
+        assert binom_ok(gone, 100000, 1 - math.exp(-nx * sg * T)), (gone, nx)
+    assert gone_edge + gone_mid == k
