@@ -261,6 +261,33 @@ int pic_get_events(pic_handle *h, int64_t max, int64_t *rec, int64_t *n, int32_t
 
 /* Collision-frequency bound used by the null-collision test of species s [1/s]
    (for O- the value of the last ion step). */
+/* Spatially resolved O2(a1Delta_g), the extension section 4 proposes for the
+   uniform n = C n(O2) of Eq. (1) (PIC_T_O2A partners).  The density on the nodes
+   is the steady state of  D n'' - quench_rate n + P(x) = 0  between the
+   electrodes, each losing gamma v / (2 (2 - gamma)) n per unit area (v the mean
+   molecular speed at t_gas), with P the production by the excitation channel
+   source_process (Table 1 (14)), tallied per node with the linear weighting of
+   the charge deposit while the discharge steps; finite volumes on the nodes,
+   FP64, solved on the device.
+   pic_metastable_config: validates, starts from n = C n(O2) everywhere and
+     clears the tally (asynchronous).  PIC_EINVAL: source_process not an
+     electron excitation, diffusion <= 0, quench_rate < 0, surface_loss outside
+     [0, 1], or no loss at all.
+   pic_metastable_update: solves from the events since the config or the last
+     update, P = w (events at the node) / (volume x elapsed time), and uses the
+     new profile for Eq. (1) detachment and the O- collision bound from the next
+     step on; copies the ng + 1 densities [m^-3] to n_out (host, may be NULL;
+     then asynchronous).  PIC_EINVAL before a config or with no step since the
+     last update. */
+typedef struct pic_metastable {
+  int32_t source_process;  /* index in the process list of the e + O2 -> e + O2(a) channel */
+  double diffusion;        /* D of O2(a) in O2 at the run's pressure [m^2/s] */
+  double quench_rate;      /* volume loss rate [1/s] */
+  double surface_loss;     /* loss probability per wall collision, both electrodes */
+} pic_metastable;
+int pic_metastable_config(pic_handle *h, const pic_metastable *m);
+int pic_metastable_update(pic_handle *h, double *n_out);
+
 int pic_nu_max(pic_handle *h, int32_t s, double *nu);
 
 /* Timing of the kernels of the next n_steps steps (synchronises): total device

@@ -1128,6 +1128,13 @@ int orc_metastable_update(orc_sim *S, double *n_out) {
   return 0;
 }
 
+/* test hook: a given O2(a) profile (after a config) */
+int orc_metastable_set(orc_sim *S, const double *na) {
+  if (!S->meta_on) return -1;
+  memcpy(S->na, na, sizeof(double) * (S->c.ng + 1));
+  return 0;
+}
+
 void orc_metastable_tally(const orc_sim *S, int64_t *src) {
   memcpy(src, S->meta_src, sizeof(int64_t) * (S->c.ng + 1));
 }

@@ -154,6 +154,7 @@ void orc_get_current(const orc_sim *S, double *jsum, int64_t *jcnt, double *psum
 int orc_metastable_config(orc_sim *S, int32_t proc, double D, double nu_q, double gamma);
 int orc_metastable_update(orc_sim *S, double *n_out);
 void orc_metastable_tally(const orc_sim *S, int64_t *src);
+int orc_metastable_set(orc_sim *S, const double *na);   /* test hook */
 void orc_metastable_solve(int32_t ng, double dx, double D, double nu_q, double h, const double *prod, double *n);
 
 /* event log: records of 6 int64 {step, species, id, code, band, aux};

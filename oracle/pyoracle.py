@@ -111,6 +111,8 @@ def lib():
         L.orc_metastable_update.restype = i32
         L.orc_metastable_update.argtypes = [vp, vp]
         L.orc_metastable_tally.argtypes = [vp, vp]
+        L.orc_metastable_set.restype = i32
+        L.orc_metastable_set.argtypes = [vp, vp]
         L.orc_metastable_solve.argtypes = [i32, dbl, dbl, dbl, dbl, vp, vp]
         _lib = L
     return _lib
@@ -318,6 +320,12 @@ class Oracle:
         if lib().orc_metastable_update(self.h, _p(n)) != 0:
             raise ValueError("metastable update without configuration or tally window")
         return n
+
+    def metastable_set(self, n):
+        """Test hook: use the given O2(a) profile [ng + 1] (after metastable_config)."""
+        n = np.ascontiguousarray(n, dtype=np.float64)
+        if lib().orc_metastable_set(self.h, _p(n)) != 0:
+            raise ValueError("metastable_set before metastable_config")
 
     def metastable_tally(self):
         q = np.zeros(self.ng + 1, dtype=np.int64)

@@ -36,7 +36,7 @@ EXPORTS = ("pic_version", "pic_query", "pic_create", "pic_destroy", "pic_load_un
            "pic_nu_max", "pic_step_timed", "pic_strerror", "pic_last_error",
            "pic_batch_query", "pic_batch_create", "pic_batch_step_cycles", "pic_batch_sync",
            "pic_batch_set_config", "pic_batch_get_config", "pic_batch_autotune", "pic_batch_destroy",
-           "pic_batch_last_error", "pic_ksub_select")
+           "pic_batch_last_error", "pic_ksub_select", "pic_metastable_config", "pic_metastable_update")
 MLP_EXPORTS = ("mlp_query", "mlp_create", "mlp_destroy", "mlp_set_params", "mlp_get_params", "mlp_forward",
                "mlp_backward", "mlp_get_grads", "mlp_adam", "mlp_last_error")
 MLP_NPARAM = 199942
@@ -67,6 +67,11 @@ class pic_species(C.Structure):
 class pic_process(C.Structure):
     _fields_ = [("species", C.c_int32), ("kind", C.c_int32), ("target", C.c_int32), ("e_th", C.c_double),
                 ("target_mass", C.c_double), ("sigma", C.POINTER(C.c_double))]
+
+
+class pic_metastable(C.Structure):
+    _fields_ = [("source_process", C.c_int32), ("diffusion", C.c_double), ("quench_rate", C.c_double),
+                ("surface_loss", C.c_double)]
 
 
 class pic_moments_out(C.Structure):
@@ -117,6 +122,8 @@ def lib():
         L.pic_get_counters.argtypes = [vp, vp]
         L.pic_get_events.argtypes = [vp, i64, vp, P(i64), i32]
         L.pic_nu_max.argtypes = [vp, i32, P(dbl)]
+        L.pic_metastable_config.argtypes = [vp, P(pic_metastable)]
+        L.pic_metastable_update.argtypes = [vp, vp]
         L.pic_step_timed.argtypes = [vp, i64, P(dbl), P(dbl), P(i64)]
         L.pic_strerror.restype = C.c_char_p
         L.pic_strerror.argtypes = [i32]
@@ -323,6 +330,17 @@ def pic_get_events(h, max_records, clear=False):
     return rec[:min(n.value, max_records)], n.value
 
 
+def pic_metastable_config(h, source_process, diffusion, quench_rate, surface_loss):
+    m = pic_metastable(int(source_process), float(diffusion), float(quench_rate), float(surface_loss))
+    _check(lib().pic_metastable_config(h, C.byref(m)), h)
+
+
+def pic_metastable_update(h, ng):
+    n = np.zeros(ng + 1)
+    _check(lib().pic_metastable_update(h, _ptr(n)), h)
+    return n
+
+
 def pic_nu_max(h, s):
     v = C.c_double(0)
     _check(lib().pic_nu_max(h, s, C.byref(v)), h)
@@ -426,6 +444,15 @@ class Discharge:
 
     def nu_max(self, s):
         return pic_nu_max(self.h, s)
+
+    def metastable_config(self, source_process, diffusion, quench_rate, surface_loss):
+        """Spatially resolved O2(a): production by process index source_process,
+        diffusion [m^2/s], volume loss [1/s], surface loss probability."""
+        pic_metastable_config(self.h, source_process, diffusion, quench_rate, surface_loss)
+
+    def metastable_update(self):
+        """Solve the O2(a) profile from the production since the last update; [ng + 1] m^-3."""
+        return pic_metastable_update(self.h, self.ng)
 
     def step_timed(self, n):
         return pic_step_timed(self.h, n)

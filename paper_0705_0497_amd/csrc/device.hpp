@@ -52,7 +52,10 @@ struct Scalars {
   double numax_ei;                 // electron-ion bound of the current ion step [1/s]
   double pnull_ei;                 // 1 - exp(-numax_ei dt_i)
   float inv_numax_ei;
+  int32_t meta_on;                 // spatially resolved O2(a): the field below replaces C n(O2)
+  int32_t meta_tab;                // process whose events produce O2(a) (Table 1 (14))
   int32_t pad3;
+  double na_max;                   // largest node density of the O2(a) field [m^-3]
   unsigned long long nsort[NSP];   // slots seen by the running sort
   // current density at the driven electrode: state of the previous field solve
   double e0_prev, u_prev;
@@ -132,6 +135,10 @@ struct Sim {
   int32_t *kleft;                  // [ng] O2+ partners still to remove per cell
   int32_t *kleft_neg;              // [ng] O- partners still to remove per cell
   float *dens_ei;                  // [2][ng+1] O2+, O- node densities of the field solve [m^-3]
+  unsigned long long *meta_src;    // [ng+1] O2(a) production events, linear weighting in 2^-32 units
+  double *na;                      // [ng+1] O2(a) density [m^-3]
+  float *na_f;                     // [ng+1] the same in FP32 for the collision step
+  double *meta_tmp;                // [ng+1] solver work
   unsigned long long *cmin;        // [2][ng] pairing minima
   int32_t *sortcnt, *sortbase;     // [ng], [ng]
   Scalars *sc;

@@ -541,6 +541,7 @@ __device__ void collide_electron(const Sim &S, int64_t step, const Cand &q, Push
     return;
   }
   atomicAdd(&bc.c[C_EVENT + chosen], 1u);
+  if (S.sc->meta_on && chosen == S.sc->meta_tab) dep_global(S.meta_src, cell, off);   // an O2(a) is born here
   float d0, d1, d2;
   iso_dir(c.z, c.w, d0, d1, d2);
   float enew;
@@ -627,6 +628,8 @@ __device__ void collide_ion(const Sim &S, int64_t step, const Cand &q, PushShare
     const float g = cl ? sqrtf(pd.inv_mu2 * ec) : sqrtf(g2);
     float dens;
     if (pd.target == T_GRIDPOS) dens = fmaf(off, sh.N[cell + 1] - sh.N[cell], sh.N[cell]) * inv_numax;
+    else if (pd.target == T_O2A && S.sc->meta_on)
+      dens = fmaf(off, S.na_f[cell + 1] - S.na_f[cell], S.na_f[cell]) * inv_numax;
     else dens = pd.scale * (S_ == 2 ? inv_numax : 1.0f);
     const float sg = ec < pd.e_th ? 0.0f : tab_sigma(sh.tab + k * S.ntab, tab_pos(S, ec));
     acc = fmaf(dens * sg, g, acc);
@@ -982,7 +985,8 @@ __device__ void ionprep_block(const Sim &S) {
     double sum = 0.0;
     for (int p = 0; p < np; ++p) {
       const ProcDev &pd = S.proc[2][p];
-      const double n = pd.target == T_GRIDPOS ? nmax : (pd.target == T_O2A ? S.c_meta * S.n_o2 : S.n_o2);
+      const double n = pd.target == T_GRIDPOS ? nmax
+                     : pd.target == T_O2A ? (S.sc->meta_on ? S.sc->na_max : S.c_meta * S.n_o2) : S.n_o2;
       sum += n * S.hbound[(size_t)pd.tab * (S.ntab - 1) + k];
     }
     best = fmax(best, sum);
@@ -1192,6 +1196,73 @@ __global__ __launch_bounds__(BS) void k_eion(Sim S, int64_t step) {
       S.sc->pair_active_neg = 1;
     }
   }
+}
+
+// ---------------------------------------------------------------- O2(a1Delta_g) field
+// Spatially resolved O2(a), the extension section 4 proposes for n = C n(O2) in
+// Eq. (1): start from the uniform value, tally production by process tab.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_meta_init(Sim S, int tab) {
+  const int nn = S.ng + 1;
+  const double n0 = S.c_meta * S.n_o2;
+  for (int j = threadIdx.x; j < nn; j += BS) {
+    S.na[j] = n0;
+    S.na_f[j] = (float)n0;
+    S.meta_src[j] = 0ull;
+  }
+  if (threadIdx.x == 0) {
+    S.sc->meta_tab = tab;
+    S.sc->na_max = n0;
+    S.sc->meta_on = 1;
+  }
+}
+
+// Steady D n'' - nu_q n + P = 0 on the nodes (finite volumes, half volumes at the
+// electrodes, surface flux h n there), P from the events tallied over tau seconds:
+// P_j = w (tally_j 2^-32) / (V_j tau).  The tridiagonal system is solved by one
+// lane (Thomas, FP64, O(ng) dependent steps): it runs once per update, every
+// ten to hundreds of rf cycles.
+template <int BS>
+__global__ __launch_bounds__(BS) void k_meta_solve(Sim S, double weight, double tau, double D, double nu_q, double h) {
+  __shared__ double red[BS];
+  const int ng = S.ng, nn = ng + 1;
+  const double dx = S.dx;
+  for (int j = threadIdx.x; j < nn; j += BS) {
+    const double vol = (j == 0 || j == ng) ? 0.5 * dx : dx;
+    S.na[j] = -(weight * ((double)(long long)S.meta_src[j] / 4294967296.0) / (vol * tau));   // right-hand side
+    S.meta_src[j] = 0ull;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double k = D / (dx * dx);
+    double *cp = S.meta_tmp, *x = S.na;
+    // forward sweep: x holds the modified right-hand side
+    double b = -2.0 * k - 2.0 * h / dx - nu_q, c = 2.0 * k;
+    cp[0] = c / b;
+    x[0] = x[0] / b;
+    for (int j = 1; j < nn; ++j) {
+      const double a = j == ng ? 2.0 * k : k;
+      b = j == ng ? -2.0 * k - 2.0 * h / dx - nu_q : -2.0 * k - nu_q;
+      c = j == ng ? 0.0 : k;
+      const double m = b - a * cp[j - 1];
+      cp[j] = c / m;
+      x[j] = (x[j] - a * x[j - 1]) / m;
+    }
+    for (int j = nn - 2; j >= 0; --j) x[j] = x[j] - cp[j] * x[j + 1];
+  }
+  __syncthreads();
+  double m = 0.0;
+  for (int j = threadIdx.x; j < nn; j += BS) {
+    S.na_f[j] = (float)S.na[j];
+    m = fmax(m, S.na[j]);
+  }
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = BS / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) S.sc->na_max = red[0];
 }
 
 // ---------------------------------------------------------------- cell sort
@@ -1738,6 +1809,16 @@ hipError_t launch_ionprep(const Sim &S, hipStream_t st) {
 
 hipError_t launch_pair(const Sim &S, int64_t step, int r, int sp, int grid, hipStream_t st) {
   hipLaunchKernelGGL((k_pair<GBS>), dim3(grid), dim3(GBS), 0, st, S, step, r, sp);
+  return hipGetLastError();
+}
+
+hipError_t launch_meta_init(const Sim &S, int tab, hipStream_t st) {
+  hipLaunchKernelGGL((k_meta_init<GBS>), dim3(1), dim3(GBS), 0, st, S, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_meta_solve(const Sim &S, double weight, double tau, double D, double nu_q, double h, hipStream_t st) {
+  hipLaunchKernelGGL((k_meta_solve<GBS>), dim3(1), dim3(GBS), 0, st, S, weight, tau, D, nu_q, h);
   return hipGetLastError();
 }
 

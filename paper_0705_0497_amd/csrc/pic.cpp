@@ -20,6 +20,8 @@ hipError_t launch_fixup(const Sim &S, hipStream_t st);
 hipError_t launch_ionprep(const Sim &S, hipStream_t st);
 hipError_t launch_pair(const Sim &S, int64_t step, int r, int sp, int grid, hipStream_t st);
 hipError_t launch_eiprep(const Sim &S, hipStream_t st);
+hipError_t launch_meta_init(const Sim &S, int tab, hipStream_t st);
+hipError_t launch_meta_solve(const Sim &S, double weight, double tau, double D, double nu_q, double h, hipStream_t st);
 hipError_t launch_eion(const Sim &S, int64_t step, int grid, hipStream_t st);
 hipError_t launch_sort(const Sim &S, int s, const Particles &dst, int grid, hipStream_t st);
 hipError_t launch_diag(const Sim &S, int s, int grid, hipStream_t st);
@@ -61,7 +63,8 @@ struct Layout {
   size_t part[NSP][2][6];   // two buffers x (w, off, vx, vy, vz, id)
   size_t pkey[NSP], pbkt[NSP], ptmp[NSP], bcnt;
   size_t Q, E, phi, sumQ, sumphi, esum, ecnt, edf, iedf, nacc, kleft, cmin, sortcnt, sortbase, sc, sigma,
-      hbound, events, partials, ttot, blkcnt, prof, jsum, jcnt, jpow, kleft_neg, dens_ei;
+      hbound, events, partials, ttot, blkcnt, prof, jsum, jcnt, jpow, kleft_neg, dens_ei, meta_src, na, na_f,
+      meta_tmp;
   size_t take(size_t bytes) {
     const size_t o = total;
     total += (bytes + 255) & ~(size_t)255;
@@ -108,6 +111,10 @@ Layout make_layout(const pic_config &c, const pic_species *sp, int nproc) {
   L.jpow = L.take(16);
   L.kleft_neg = L.take(4 * (size_t)c.ng);          // O- partners of electron-impact detachment
   L.dens_ei = L.take(4 * 2 * nn);                   // ion node densities for the electron-ion test
+  L.meta_src = L.take(8 * nn);                      // O2(a) field: production tally, density, solver work
+  L.na = L.take(8 * nn);
+  L.na_f = L.take(4 * nn);
+  L.meta_tmp = L.take(8 * nn);
   return L;
 }
 
@@ -194,6 +201,11 @@ struct pic_handle {
   int ncu = 1;
   bool batch_busy = false;         // stepped by a batch that has not been synchronised
   std::string err;
+  // spatially resolved O2(a): configuration and the step its tally window began
+  bool meta_on = false;
+  pic_metastable meta{};
+  double meta_h = 0.0;
+  int64_t meta_step0 = 0;
 };
 
 namespace {
@@ -420,6 +432,10 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
   S.kleft = (int32_t *)(ws + L.kleft);
   S.kleft_neg = (int32_t *)(ws + L.kleft_neg);
   S.dens_ei = (float *)(ws + L.dens_ei);
+  S.meta_src = (unsigned long long *)(ws + L.meta_src);
+  S.na = (double *)(ws + L.na);
+  S.na_f = (float *)(ws + L.na_f);
+  S.meta_tmp = (double *)(ws + L.meta_tmp);
   S.cmin = (unsigned long long *)(ws + L.cmin);
   S.sortcnt = (int32_t *)(ws + L.sortcnt);
   S.bcnt = (int32_t *)(ws + L.bcnt);
@@ -934,6 +950,39 @@ int pic_get_events(pic_handle *h, int64_t max, int64_t *rec, int64_t *n, int32_t
     if (r != PIC_OK) return r;
   }
   return device_errors(h, sc);
+}
+
+int pic_metastable_config(pic_handle *h, const pic_metastable *m) {
+  if (!h || !m) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
+  const int p = m->source_process;
+  if (p < 0 || p >= (int)h->pr.size() || h->pr[p].species != 0 || h->pr[p].kind != PIC_EXCITE)
+    return fail(h, PIC_EINVAL, "source_process must index an electron excitation channel");
+  if (!(std::isfinite(m->diffusion) && m->diffusion > 0.0) || !(std::isfinite(m->quench_rate) && m->quench_rate >= 0.0) ||
+      !(m->surface_loss >= 0.0 && m->surface_loss <= 1.0) || (m->surface_loss == 0.0 && m->quench_rate == 0.0))
+    return fail(h, PIC_EINVAL, "need diffusion > 0, quench_rate >= 0, surface_loss in [0, 1], and some loss");
+  const double vbar = std::sqrt(8.0 * KB * h->cfg.t_gas / (3.14159265358979323846 * h->pr[p].target_mass));
+  h->meta = *m;
+  h->meta_h = m->surface_loss * vbar / (2.0 * (2.0 - m->surface_loss));
+  h->meta_on = true;
+  h->meta_step0 = h->step;
+  HIPCHK(h, launch_meta_init(h->S, p, h->stream));
+  return PIC_OK;
+}
+
+int pic_metastable_update(pic_handle *h, double *n_out) {
+  if (!h) return PIC_EINVAL;
+  if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
+  if (!h->meta_on) return fail(h, PIC_EINVAL, "pic_metastable_config has not been called");
+  const double tau = (double)(h->step - h->meta_step0) * h->S.dt;
+  if (!(tau > 0.0)) return fail(h, PIC_EINVAL, "no steps since the last update");
+  HIPCHK(h, launch_meta_solve(h->S, h->cfg.weight, tau, h->meta.diffusion, h->meta.quench_rate, h->meta_h, h->stream));
+  h->meta_step0 = h->step;
+  if (n_out) {
+    HIPCHK(h, hipMemcpyAsync(n_out, h->S.na, 8 * (size_t)(h->cfg.ng + 1), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+  }
+  return PIC_OK;
 }
 
 int pic_nu_max(pic_handle *h, int32_t s, double *nu) {

@@ -446,3 +446,88 @@ def test_electron_ion_channels_single_step_element_by_element(step0):
         np.testing.assert_array_equal(gc[:po.C_CLAMP], oc[:po.C_CLAMP])
         np.testing.assert_array_equal(gc[po.C_EICAND:po.C_DEFICIT_NEG + 1], oc[po.C_EICAND:po.C_DEFICIT_NEG + 1])
         assert all(g.count(s) == o.count(s) for s in range(3))
+
+
+def _with_a1(factor=20.0):
+    # the eight workload channels plus O2(a1Delta_g) excitation (Table 1 (14)), boosted so that
+    # a few steps give a production profile; index of the new channel
+    procs = H.neutralising(I.make_processes())
+    a1 = next(p for p in I.make_processes_full() if p.name == "e-a1")
+    a1.sigma = a1.sigma * factor
+    k = max(i for i, p in enumerate(procs) if p.species == 0) + 1
+    procs.insert(k, a1)
+    return procs, k
+
+
+META = dict(diffusion=0.1, quench_rate=20.0, surface_loss=0.05)
+
+
+@pytest.mark.gpu
+def test_metastable_tally_and_solve_match_the_event_positions():
+    """O2(a) production from the GPU's own events: the tally is the exact deposit of the
+    electrons that excited O2(a), and the device solve equals the oracle's solver on it."""
+    d = I.config(1)
+    procs, ka1 = _with_a1(factor=80.0)
+    o, g, st = _pair(d, procs, None, seed_steps=30)      # continue after the seed run: fresh draws
+    g.metastable_config(ka1, META["diffusion"], META["quench_rate"], META["surface_loss"])
+    o.metastable_config(ka1, META["diffusion"], META["quench_rate"], META["surface_loss"])
+    g.clear_events()
+    o.log_events(True)
+    steps = 1                                # the events' positions are those after this step
+    g.step(steps)
+    o.step(steps)
+    gev = g.events()
+    hits = gev[(gev[:, 1] == 0) & (gev[:, 3] == ka1)][:, 2]
+    assert len(hits) >= 20
+    n_g = g.metastable_update()
+    n_o = o.metastable_update()
+    gs, _ = g.get_particles(0)
+    sel = np.isin(gs["id"], hits)
+    assert sel.sum() == len(hits)           # excitation keeps the electron
+    tally = po.deposit_canonical(d.ng, gs["cell"][sel], gs["off"][sel])
+    dx = d.L / d.ng
+    vol = np.full(d.ng + 1, dx)
+    vol[0] = vol[-1] = dx / 2
+    prod = d.weight * (tally / 2.0 ** 32) / (vol * steps * d.dt)
+    vbar = math.sqrt(8 * 1.380649e-23 * d.t_gas / (math.pi * I.M_O2))
+    h = META["surface_loss"] * vbar / (2 * (2 - META["surface_loss"]))
+    n_exp = po.metastable_solve(d.ng, dx, META["diffusion"], META["quench_rate"], h, prod)
+    np.testing.assert_allclose(n_g, n_exp, rtol=1e-12, atol=0)
+    # the oracle's own update from its FP64 positions: the same events, positions within 1e-5 cell
+    np.testing.assert_allclose(n_g, n_o, rtol=5e-4)
+
+
+@pytest.mark.gpu
+def test_detachment_on_the_resolved_density_single_step():
+    """Eq. (1) detachment against the O2(a) profile the GPU solved: the oracle takes the
+    GPU's state and profile after the production steps, then both run the ion step."""
+    d = I.config(1)
+    procs, ka1 = _with_a1()
+    for p in procs:
+        if p.target == "O2a":
+            p.sigma = p.sigma * 300.0            # Eq. (1) made frequent at the small O2(a) densities
+    st, nid, sidx = H.canonical_from_oracle(d, procs, 30)
+    assert sidx % d.ksub == 0
+    # continue after the seed run (its draws are not replayed): production steps, then an ion step
+    g = H.gpu_from_canonical(d, procs, st, nid, sidx + 1, event_capacity=EVCAP)
+    g.metastable_config(ka1, META["diffusion"], META["quench_rate"], META["surface_loss"])
+    g.step(d.ksub - 1)
+    n_g = g.metastable_update()
+    assert n_g.max() > 1.3 * n_g.min()         # a profile, not the uniform start
+    gst = [g.get_particles(s) for s in range(3)]
+    o = H.oracle_from_canonical(d, procs, [x[0] for x in gst], [x[1] for x in gst], sidx + d.ksub)
+    o.metastable_config(ka1, META["diffusion"], META["quench_rate"], META["surface_loss"])
+    o.metastable_set(n_g)
+    g.clear_events()
+    o.log_events(True)
+    o.step(1)                                    # the ion step, detachment on the resolved field
+    g.step(1)
+    gev, oev = g.events(), o.events()
+    ad = [i for i, p in enumerate(procs) if p.target == "O2a"][0]
+    assert np.sum(oev[:, 3] == ad) >= 3
+    bad, band = H.compare_events(gev, oev)
+    assert not bad, f"decisions differ outside the band: {bad[:10]}"
+    for s in range(3):
+        gs, _ = g.get_particles(s)
+        dx_, dv = H.compare_states(gs, o.get_particles(s), d.species()[s], skip=band, s=s)
+        assert dx_ <= H.POS_TOL and dv <= H.VEL_TOL, (s, dx_, dv)
