@@ -110,6 +110,92 @@ def run(c_values=C_VALUES, n_total=120000, max_cycles=3000, avg_cycles=100, seed
     return out
 
 
+# O2(a1Delta_g) transport (order-of-magnitude values, not from the paper): diffusion
+# from O2 self-diffusion, 0.2 cm^2/s at 1 atm (D p = 2.0 m^2 Pa / s); quenching by
+# O2 at 1.5e-24 m^3/s; loss probability 5e-3 per collision with an electrode
+DP_O2A = 2.0
+K_QUENCH = 1.5e-24
+GAMMA_O2A = 5e-3
+
+
+def processes_with_a1(r_x=R_X_BOHR):
+    """processes() plus O2(a1Delta_g) excitation (Table 1 (14)) as the last electron
+    channel; returns the list and that channel's index."""
+    procs = processes(r_x)
+    a1 = next(p for p in I.make_processes_full() if p.name == "e-a1")
+    k = max(i for i, p in enumerate(procs) if p.species == 0) + 1
+    procs.insert(k, a1)
+    return procs, k
+
+
+def resolved(n_total=120000, c0=1.0 / 6.0, window=100, min_updates=20, max_updates=60, tol=0.01, seed0=7100,
+             log=None):
+    """The section 3 discharge with the O2(a) density solved from its own production
+    (updated every window cycles), beside the same discharge with the uniform
+    n = c0 n(O2); both start from c0 and run as one batch until, after at least
+    min_updates, the profile changes by less than tol between updates and the
+    electron density of both members passes the convergence test."""
+    import torch
+    stream = torch.cuda.Stream()
+    procs, ka1 = processes_with_a1()
+    members = []
+    for j in range(2):
+        g = B.Discharge(fig34_discharge(c0, seed0 + j, n_total), procs, stream=stream, max_products=1 << 16)
+        g.load_uniform()
+        members.append(g)
+    d = members[0].d
+    n_o2 = d.p / (1.380649e-23 * d.t_gas)
+    res_g = members[1]
+    res_g.metastable_config(ka1, DP_O2A / d.p, K_QUENCH * n_o2, GAMMA_O2A)
+    t0 = time.perf_counter()
+    batch = B.Batch(members, block=512, sort_every=20, use_graph=True)
+    history, n_a, prev = [], None, None
+    mons = [W.Monitor() for _ in members]
+    for g in members:
+        g.moments(reset=True)
+    for u in range(max_updates):
+        for w in range(window // W.WINDOW):
+            batch.step_cycles(W.WINDOW)
+            batch.sync()
+            for mon, g in zip(mons, members):
+                mon.add(g.moments(reset=True)["sum_q"][0], u * window + (w + 1) * W.WINDOW)
+        n_a = res_g.metastable_update()
+        change = float(np.abs(n_a - prev).sum() / np.abs(n_a).sum()) if prev is not None else 1.0
+        history.append({"cycle": (u + 1) * window, "n_a_centre": float(n_a[d.ng // 2]),
+                        "n_a_edge": float(n_a[0]), "change": change})
+        if log:
+            log(f"update {u + 1}: n(O2a) centre {n_a[d.ng // 2]:.3e}, edge {n_a[0]:.3e}, change {change:.4f}")
+        # the plasma follows the new profile: stop once both hold still
+        steady = all(len(m.passed) >= 2 and m.passed[-1] and m.passed[-2] for m in mons)
+        if u + 1 >= min_updates and change < tol and steady:
+            break
+        prev = n_a
+    for g in members:
+        g.moments(reset=True)
+    batch.step_cycles(window)
+    batch.sync()
+    batch.close()
+    out = {"c0": c0, "window": window, "updates": len(history), "history": history,
+           "transport": {"D_m2_s": DP_O2A / d.p, "quench_rate_s": K_QUENCH * n_o2, "gamma": GAMMA_O2A},
+           "n_o2": n_o2, "n_a": n_a.tolist(), "members": []}
+    for name, g in (("uniform", members[0]), ("resolved", members[1])):
+        m = g.moments(reset=True)
+        dens, mean = W.cycle_profiles(g, m)
+        k = len(W.XS) // 2
+        ne = dens[0]
+        above = W.XS[ne >= 0.5 * ne.max()]
+        out["members"].append({
+            "name": name,
+            "centre_density_m3": {"e": float(dens[0, k]), "O-": float(dens[2, k]), "O2+": float(dens[1, k])},
+            "electronegativity_centre": float(dens[2, k] / max(dens[0, k], 1.0)),
+            "fwhm_ne_over_L": float(above.max() - above.min()) if len(above) else 0.0,
+            "profiles_x": W.XS[::16].tolist(),
+            "profiles_m3": {"e": dens[0, ::16].tolist(), "O-": dens[2, ::16].tolist(), "O2+": dens[1, ::16].tolist()},
+        })
+    out["gpu_seconds"] = time.perf_counter() - t0
+    return out
+
+
 def markdown(res):
     lines = ["| C | converged at cycle | n_e centre [m^-3] | n_O- centre | n_O2+ centre | n_O- / n_e | "
              "power <U j> [W/m^2] | current rms diff vs C = 0 |",
@@ -128,13 +214,24 @@ def main(argv=None):
     ap.add_argument("--n-total", type=int, default=120000)
     ap.add_argument("--max-cycles", type=int, default=3000)
     ap.add_argument("--avg-cycles", type=int, default=100)
+    ap.add_argument("--resolved", action="store_true",
+                    help="O2(a) solved from its own production instead of the C sweep")
     args = ap.parse_args(argv)
     log = lambda s: print(s, file=sys.stderr, flush=True)
-    res = run(n_total=args.n_total, max_cycles=args.max_cycles, avg_cycles=args.avg_cycles, log=log)
+    if args.resolved:
+        res = resolved(n_total=args.n_total, log=log)
+        text = "\n".join(f"| {m['name']} | {m['centre_density_m3']['e']:.3e} | {m['centre_density_m3']['O-']:.3e} | "
+                         f"{m['centre_density_m3']['O2+']:.3e} | {m['electronegativity_centre']:.3f} | "
+                         f"{m['fwhm_ne_over_L']:.3f} |" for m in res["members"])
+        text = ("| O2(a) | n_e centre | n_O- centre | n_O2+ centre | n_O- / n_e | FWHM of n_e / L |\n"
+                "|---|---|---|---|---|---|\n" + text)
+    else:
+        res = run(n_total=args.n_total, max_cycles=args.max_cycles, avg_cycles=args.avg_cycles, log=log)
+        text = markdown(res)
     if args.out:
         with open(args.out, "w") as f:
             json.dump(res, f)
-    print(markdown(res), flush=True)
+    print(text, flush=True)
 
 
 if __name__ == "__main__":
