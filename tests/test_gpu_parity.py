@@ -531,3 +531,65 @@ def test_detachment_on_the_resolved_density_single_step():
         gs, _ = g.get_particles(s)
         dx_, dv = H.compare_states(gs, o.get_particles(s), d.species()[s], skip=band, s=s)
         assert dx_ <= H.POS_TOL and dv <= H.VEL_TOL, (s, dx_, dv)
+
+
+def _full_set_for_runs():
+    # all sixteen channels with the electron-ion rates and the O2(a) production raised so that two rf
+    # cycles of the small discharge feel them; index of the O2(a) source channel
+    procs = I.make_processes_full()
+    for k, p in enumerate(procs):
+        if p.name == "e-recomb":
+            procs[k] = I.Process("e-recomb", 0, "recomb", "grid+", 0.0, I.M_O2PLUS,
+                                 I.power_law_table(2e-15, 0.0, 0.5, 0.0), {})
+        if p.name == "e-edet":
+            procs[k] = I.Process("e-edet", 0, "edetach", "grid-", 1.461, I.M_OMINUS,
+                                 I.power_law_table(2e-15, 0.0, 0.5, 1.461), {})
+        if p.name == "e-a1":
+            p.sigma = p.sigma * 100.0
+    return procs, [p.name for p in procs].index("e-a1")
+
+
+def test_full_channel_set_with_resolved_o2a_agrees_statistically():
+    """Sixteen channels and the O2(a) profile solved after the first rf cycle (each side from
+    its own production): densities over the second cycle, 6 seeds per side, z-scores of the
+    ensemble means on 16 coarse bins, and the electron-ion event rates."""
+    from paper_0705_0497_amd.binding import Discharge
+    d = I.config(1)
+    procs, ka1 = _full_set_for_runs()
+    names = [p.name for p in procs]
+    M = 6
+    res = {"gpu": [], "orc": []}
+    ev = {"gpu": [], "orc": []}
+    for m in range(M):
+        dd = I.config(1, seed=9100 + m)
+        o = po.Oracle(dd, dd.species(), procs)
+        o.load_uniform()
+        o.prepare(True)
+        o.metastable_config(ka1, META["diffusion"], META["quench_rate"], META["surface_loss"])
+        o.step(d.steps_per_cycle)
+        o.metastable_update()
+        o.reset_moments()
+        c0 = o.counters()
+        o.step(d.steps_per_cycle)
+        res["orc"].append(o.moments()["sumQ"] / d.steps_per_cycle)
+        ev["orc"].append((o.counters() - c0)[[po.C_EVENT + names.index("e-recomb"), po.C_EVENT + names.index("e-edet")]])
+        g = Discharge(dd, procs)
+        g.load_uniform()
+        g.metastable_config(ka1, META["diffusion"], META["quench_rate"], META["surface_loss"])
+        g.step(d.steps_per_cycle)
+        g.metastable_update()
+        g.moments(reset=True)
+        c0 = g.counters()
+        g.step(d.steps_per_cycle)
+        res["gpu"].append(g.moments()["sum_q"] / d.steps_per_cycle)
+        ev["gpu"].append((g.counters() - c0)[[po.C_EVENT + names.index("e-recomb"), po.C_EVENT + names.index("e-edet")]])
+    coarse = lambda a: a[:, :, :d.ng].reshape(a.shape[0], 3, 16, -1).sum(-1)
+    G, O = coarse(np.array(res["gpu"])), coarse(np.array(res["orc"]))
+    z = (G.mean(0) - O.mean(0)) / np.sqrt(G.var(0, ddof=1) / M + O.var(0, ddof=1) / M + 1e-30)
+    assert np.mean(np.abs(z) > 3.5) <= 0.05, z
+    assert np.mean(z ** 2) < 3.0, z
+    eg, eo = np.array(ev["gpu"], float), np.array(ev["orc"], float)
+    assert np.all(eo.sum(0) > 50), eo
+    for j in range(2):                        # electron-ion event counts: ensemble means within 4 sigma
+        zj = (eg[:, j].mean() - eo[:, j].mean()) / math.sqrt(eg[:, j].var(ddof=1) / M + eo[:, j].var(ddof=1) / M + 1e-30)
+        assert abs(zj) < 4.0, (j, eg[:, j], eo[:, j])
