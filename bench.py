@@ -120,6 +120,7 @@ def main():
         g.sync()
         log(f"bench: warmup cycle {c + 1}/{args.warmup} done")
     c0 = g.counters()
+    n_start = sum(g.count(s) for s in range(3))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ms_push = 0.0
@@ -145,6 +146,8 @@ def main():
     achieved = per_launch / (mean_ms * 1e-3) / 1e9
     counts = [g.count(s) for s in range(3)]
     traffic = measured_traffic(int(dc[C_PUSH]) / launches)
+    # every superparticle counted at every electron step (ions included although they move every k_sub)
+    physical = 0.5 * (n_start + sum(counts)) * launches / elapsed
     out = {
         "metric": "particle-steps/s (push+deposit+MCC); rf cycles to steady state, warm vs cold",
         "value": value,
@@ -165,6 +168,8 @@ def main():
                    "superparticles_end": counts, "electron_pushes": int(dc[C_PUSH]),
                    "ion_pushes": int(dc[C_PUSH + 1] + dc[C_PUSH + 2]),
                    "electron_candidates": int(dc[C_CAND]), "parallelism": "single GPU"},
+        "pushes_per_step": pushes / launches,
+        "physical_particle_steps_per_s": physical,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": f"k_push<{args.block or 512},0> electron push+MCC+deposit",
