@@ -93,8 +93,8 @@ def main():
     ap.add_argument("--tune-window", type=int, default=200, help="sweep: autotuner trial length [steps]")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs one discharge on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is described in DESIGN.md, not implemented)", file=sys.stderr)
+        print(f"bench.py: one discharge runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the decomposition over several GPUs is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -2,7 +2,7 @@
 cycle-averaged profiles; the network of include/mlp.h learns (U, p, x/L) ->
 profiles on the GPU; new discharges are loaded from its prediction
 (pic_load_profiles) instead of uniformly, and the plain method, run until its
-convergence test holds, judges the result.
+convergence test holds, evaluates the result.
 
 The paper computes the quasi-stationary state reached after many rf cycles and
 reports cycle-averaged densities and energies across the gap (section 3); it

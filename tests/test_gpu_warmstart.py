@@ -1,7 +1,7 @@
 """What the learned warm start gains over the plain method: a network trained
 on the GPU (BF16 MFMA kernels) from the converged profiles of batched cold runs
 loads held-out discharges close to their steady state; the plain method, run
-until its convergence test holds, judges both starts.  Small version of the
+until its convergence test holds, evaluates both starts.  Small version of the
 benchmark experiment (8 training runs, 2 held-out points)."""
 import numpy as np
 import pytest
