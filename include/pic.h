@@ -60,7 +60,7 @@ extern "C" {
 /* electron collisions with the ions of the grid, tested once per ion step after
    the electron push (probability 1 - exp(-nu_ei ksub dt), nu_ei from the largest
    ion node densities of the field solve, the ion at rest); the struck ion is the
-   pairing partner in the electron's cell.  Single discharges only (not batches). */
+   pairing partner in the electron's cell.  Batches run them per member. */
 #define PIC_RECOMB 8       /* e + O2+ -> O + O (16): electron and an O2+ removed; target PIC_T_GRIDPOS */
 #define PIC_EDETACH 9      /* e + O- -> O + 2e (22): E - e_th shared (1 - r, r) by the two electrons,
                               isotropic; an O- removed; target PIC_T_GRIDNEG */

@@ -1084,7 +1084,7 @@ __global__ __launch_bounds__(BS) void k_pair(Sim S, int64_t step, int r, int sp)
 // histograms, and nu_ei = max over the table intervals of sum_q n_max,q H_q
 // (H: largest sigma g of the interval, the ion at rest).
 template <int BS>
-__global__ __launch_bounds__(BS) void k_eiprep(Sim S) {
+__device__ void eiprep_block(const Sim &S) {
   __shared__ double red[BS];
   const int ng = S.ng, nn = ng + 1;
   double nmax[2];
@@ -1128,6 +1128,9 @@ __global__ __launch_bounds__(BS) void k_eiprep(Sim S) {
   }
 }
 
+template <int BS>
+__global__ __launch_bounds__(BS) void k_eiprep(Sim S) { eiprep_block<BS>(S); }
+
 // Table 1 (16) e + O2+ -> O + O and (22) e + O- -> O + 2e, once per ion step after
 // the electron push: every electron present at the start of the step is a
 // candidate with probability 1 - exp(-nu_ei dt_i); the channel follows from
@@ -1137,14 +1140,14 @@ __global__ __launch_bounds__(BS) void k_eiprep(Sim S) {
 // as (1 - r, r) by the electron and a new one, both isotropic; an O- of the cell
 // goes to the pairing.
 template <int BS>
-__global__ __launch_bounds__(BS) void k_eion(Sim S, int64_t step) {
+__device__ void eion_run(const Sim &S, int64_t step, int bx, int gx) {
   const double pnull = S.sc->pnull_ei;
   if (!(pnull > 0.0)) return;
   const float inv_nu = S.sc->inv_numax_ei;
   const Particles &P = S.p[0];
   const int64_t N = (int64_t)S.sc->n[0];
   const int nn = S.ng + 1, n0 = S.nproc_sp[0];
-  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
+  for (int64_t i = (int64_t)bx * BS + threadIdx.x; i < N; i += (int64_t)gx * BS) {
     const int32_t w = P.w[i];
     if (w < 0) continue;
     const uint32_t id = P.id[i];
@@ -1197,6 +1200,9 @@ __global__ __launch_bounds__(BS) void k_eion(Sim S, int64_t step) {
     }
   }
 }
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_eion(Sim S, int64_t step) { eion_run<BS>(S, step, blockIdx.x, gridDim.x); }
 
 // ---------------------------------------------------------------- O2(a1Delta_g) field
 // Spatially resolved O2(a), the extension section 4 proposes for n = C n(O2) in
@@ -1677,10 +1683,22 @@ __global__ __launch_bounds__(BS) void k_ionprep_b(const Sim *__restrict__ sims, 
 
 template <int BS>
 __global__ __launch_bounds__(BS) void k_pair_b(const Sim *__restrict__ sims, const BatchDev *__restrict__ bd,
-                                                uint64_t mask, int rel, int r) {
+                                                uint64_t mask, int rel, int r, int sp) {
   const int m = blockIdx.y;
   if (!in_mask(mask, m) || r > sims[m].pair_rounds) return;
-  pair_block<BS>(sims[m], bd->base[m] + rel, r, 1);
+  pair_block<BS>(sims[m], bd->base[m] + rel, r, sp);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_eiprep_b(const Sim *__restrict__ sims, uint64_t mask) {
+  if (in_mask(mask, blockIdx.x)) eiprep_block<BS>(sims[blockIdx.x]);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_eion_b(const Sim *__restrict__ sims, const BatchDev *__restrict__ bd,
+                                               uint64_t mask, int rel) {
+  const int m = blockIdx.y;
+  if (in_mask(mask, m)) eion_run<BS>(sims[m], bd->base[m] + rel, blockIdx.x, gridDim.x);
 }
 
 template <int BS>
@@ -1939,8 +1957,18 @@ hipError_t launch_ionprep_b(const BatchLaunch &B, uint64_t mask, hipStream_t st)
   return hipGetLastError();
 }
 
-hipError_t launch_pair_b(const BatchLaunch &B, uint64_t mask, int rel, int r, hipStream_t st) {
-  hipLaunchKernelGGL((k_pair_b<GBS>), dim3(B.pgrid, B.nmem), dim3(GBS), 0, st, B.sims, B.bd, mask, rel, r);
+hipError_t launch_pair_b(const BatchLaunch &B, uint64_t mask, int rel, int r, int sp, hipStream_t st) {
+  hipLaunchKernelGGL((k_pair_b<GBS>), dim3(B.pgrid, B.nmem), dim3(GBS), 0, st, B.sims, B.bd, mask, rel, r, sp);
+  return hipGetLastError();
+}
+
+hipError_t launch_eiprep_b(const BatchLaunch &B, uint64_t mask, hipStream_t st) {
+  hipLaunchKernelGGL((k_eiprep_b<FBS>), dim3(B.nmem), dim3(FBS), 0, st, B.sims, mask);
+  return hipGetLastError();
+}
+
+hipError_t launch_eion_b(const BatchLaunch &B, uint64_t mask, int rel, hipStream_t st) {
+  hipLaunchKernelGGL((k_eion_b<GBS>), dim3(64, B.nmem), dim3(GBS), 0, st, B.sims, B.bd, mask, rel);
   return hipGetLastError();
 }
 

@@ -42,7 +42,9 @@ hipError_t launch_field_b(const BatchLaunch &B, int rel, hipStream_t st);
 hipError_t launch_push_b(const BatchLaunch &B, int s, uint64_t mask, int rel, hipStream_t st);
 hipError_t launch_reduce_b(const BatchLaunch &B, int s, uint64_t mask, hipStream_t st);
 hipError_t launch_ionprep_b(const BatchLaunch &B, uint64_t mask, hipStream_t st);
-hipError_t launch_pair_b(const BatchLaunch &B, uint64_t mask, int rel, int r, hipStream_t st);
+hipError_t launch_pair_b(const BatchLaunch &B, uint64_t mask, int rel, int r, int sp, hipStream_t st);
+hipError_t launch_eiprep_b(const BatchLaunch &B, uint64_t mask, hipStream_t st);
+hipError_t launch_eion_b(const BatchLaunch &B, uint64_t mask, int rel, hipStream_t st);
 hipError_t launch_diag_b(const BatchLaunch &B, uint64_t mask, hipStream_t st);
 hipError_t launch_compact_b(const BatchLaunch &B, uint64_t mask, hipStream_t st);
 hipError_t launch_advance_b(const BatchLaunch &B, int64_t add, hipStream_t st);
@@ -1120,7 +1122,7 @@ int launch_batch_step(pic_batch *b, int r) {
   hipStream_t st = b->stream;
   const int n = B.nmem;
   const uint64_t all = all_mask(n);
-  uint64_t dmask = 0ull, imask = 0ull;
+  uint64_t dmask = 0ull, imask = 0ull, emask = 0ull;
   int R = 0;
   for (int m = 0; m < n; ++m) {
     const pic_config &c = b->mem[m]->cfg;
@@ -1128,20 +1130,26 @@ int launch_batch_step(pic_batch *b, int r) {
     if (r % c.ksub == 0) {
       imask |= 1ull << m;
       R = std::max(R, c.pair_rounds);
+      // electron-ion channels (Table 1 (16), (22)) on this member's ion steps
+      if (b->mem[m]->S.nei > 0 && !(c.flags & PIC_F_NO_COLL)) emask |= 1ull << m;
     }
   }
+  if (emask) BHIP(b, launch_eiprep_b(B, emask, st));      // before the field kernel clears the ion histograms
   BHIP(b, launch_field_b(B, r, st));
   if (dmask) BHIP(b, launch_diag_b(B, dmask, st));
   if (b->cfg.sort_every > 0 && r % b->cfg.sort_every == 0) BHIP(b, launch_compact_b(B, all, st));
   BHIP(b, launch_push_b(B, 0, all, r, st));
   BHIP(b, launch_reduce_b(B, 0, all, st));
+  if (emask) BHIP(b, launch_eion_b(B, emask, r, st));
   if (imask) {
     BHIP(b, launch_push_b(B, 1, imask, r, st));
     BHIP(b, launch_reduce_b(B, 1, imask, st));
     BHIP(b, launch_ionprep_b(B, imask, st));
     BHIP(b, launch_push_b(B, 2, imask, r, st));
     BHIP(b, launch_reduce_b(B, 2, imask, st));
-    for (int k = 0; k <= R; ++k) BHIP(b, launch_pair_b(B, imask, r, k, st));
+    for (int k = 0; k <= R; ++k) BHIP(b, launch_pair_b(B, imask, r, k, 1, st));
+    if (emask)
+      for (int k = 0; k <= R; ++k) BHIP(b, launch_pair_b(B, emask, r, k, 2, st));
   }
   if (r == b->spc - 1) BHIP(b, launch_advance_b(B, b->spc, st));
   return PIC_OK;
@@ -1197,8 +1205,6 @@ int pic_batch_create(pic_handle *const *members, int32_t n, const pic_batch_conf
       if (members[k] == h) return bfail(nullptr, PIC_EINVAL, who + "listed twice");
     if (h->batch_busy) return bfail(nullptr, PIC_EBUSY, who + "busy in another batch");
     if (h->stream != (hipStream_t)stream) return bfail(nullptr, PIC_EINVAL, who + "created on another stream");
-    if (h->S.nei > 0)
-      return bfail(nullptr, PIC_EINVAL, who + "has electron-ion channels, which only single discharges run");
     const pic_config &c = h->cfg;
     if (c.steps_per_cycle != spc) return bfail(nullptr, PIC_EINVAL, who + "steps_per_cycle differs");
     if (spc % c.ksub != 0) return bfail(nullptr, PIC_EINVAL, who + "ksub must divide steps_per_cycle");

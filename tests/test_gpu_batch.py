@@ -150,10 +150,6 @@ def test_batch_validation_and_busy_members():
         B.Batch([mem[0], bad])
     with pytest.raises(B.PicError):
         B.Batch([mem[0], mem[0]])
-    eion = B.Discharge(ds[1], I.make_processes_full(), stream=stream)   # electron-ion channels: single runs only
-    with pytest.raises(B.PicError) as e:
-        B.Batch([mem[0], eion])
-    assert e.value.code == B.PIC_EINVAL
     with pytest.raises(B.PicError):
         B.Batch(mem, sort_every=7)                           # does not divide the cycle
     b = B.Batch(mem, sort_every=20)
@@ -166,4 +162,53 @@ def test_batch_validation_and_busy_members():
     mem[0].step(1)                                           # off the cycle boundary
     with pytest.raises(B.PicError):
         b.step_cycles(1)
+    b.close()
+
+
+def _full_channels():
+    # all sixteen channels, the electron-ion ones with sigma ~ E^-1/2 large enough to act in a few
+    # cycles; index of the O2(a) production channel
+    procs = I.make_processes_full()
+    for k, p in enumerate(procs):
+        if p.kind in ("recomb", "edetach"):
+            procs[k] = I.Process(p.name, 0, p.kind, p.target, p.e_th, p.target_mass,
+                                 I.power_law_table(3e-15, 0.0, 0.5, p.e_th), {})
+    return procs, [p.name for p in procs].index("e-a1")
+
+
+def test_batch_with_all_channels_and_resolved_o2a_equals_alone():
+    """Members with the electron-ion channels and the O2(a) profile (updated after the first
+    cycle on both sides) reach bit for bit the states of the same discharges run alone."""
+    import torch
+    from paper_0705_0497_amd.binding import Batch, Discharge
+    stream = torch.cuda.Stream()
+    ds = _members(SPEC[:3])
+    procs, ka1 = _full_channels()
+    meta = (ka1, 0.1, 20.0, 0.05)
+    ref = []
+    for d in ds:
+        g = Discharge(d, procs, stream=stream)
+        g.load_uniform()
+        g.metastable_config(*meta)
+        g.step(SPC)
+        n_a = g.metastable_update()
+        g.step(SPC)
+        ref.append((_snapshot(g), n_a))
+        g.close()
+    mem = _loaded(ds, procs, stream)
+    for g in mem:
+        g.metastable_config(*meta)
+    b = Batch(mem, block=256, sort_every=10, use_graph=True)
+    b.step_cycles(1)
+    b.sync()
+    for m, g in enumerate(mem):
+        np.testing.assert_array_equal(g.metastable_update(), ref[m][1], err_msg=f"member {m} O2(a)")
+    b.step_cycles(1)
+    b.sync()
+    for m, g in enumerate(mem):
+        snap = _snapshot(g)
+        _same(snap, ref[m][0], f"member {m}")
+        names = [p.name for p in procs]
+        c = snap["counters"]
+        assert c[18 + names.index("e-recomb")] + c[18 + names.index("e-edet")] > 0, m
     b.close()
