@@ -593,3 +593,36 @@ def test_full_channel_set_with_resolved_o2a_agrees_statistically():
     for j in range(2):                        # electron-ion event counts: ensemble means within 4 sigma
         zj = (eg[:, j].mean() - eo[:, j].mean()) / math.sqrt(eg[:, j].var(ddof=1) / M + eo[:, j].var(ddof=1) / M + 1e-30)
         assert abs(zj) < 4.0, (j, eg[:, j], eo[:, j])
+
+
+def test_parity_workload_over_two_cycles_matches_the_stored_oracle_ensemble():
+    """512-cell discharge, the oracle's 8-seed ensemble of second-cycle densities stored by
+    tests/golden/make_cfg2_ensemble.py: the GPU runs the same seeds and its ensemble agrees on
+    32 coarse bins per species (z-scores) and in the central electronegativity."""
+    import os
+    from paper_0705_0497_amd.binding import Discharge
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg2_oracle_ensemble.txt")
+    rows = [line.split() for line in open(path) if not line.startswith("#")]
+    seeds = [int(r[0]) for r in rows]
+    ao = np.array([float(r[1]) for r in rows])
+    O = np.array([[float(x) for x in r[2:]] for r in rows]).reshape(len(rows), 3, -1)
+    bins = O.shape[2]
+    G, ag = [], []
+    for seed in seeds:
+        d = I.config(2, seed=seed)
+        g = Discharge(d, I.make_processes())
+        g.load_uniform()
+        g.step(d.steps_per_cycle)
+        g.moments(reset=True)
+        g.step(d.steps_per_cycle)
+        q = g.moments()["sum_q"] / d.steps_per_cycle
+        G.append(q[:, :d.ng].reshape(3, bins, -1).sum(-1))
+        mid = slice(int(0.45 * d.ng), int(0.55 * d.ng) + 1)
+        ag.append(q[2, mid].sum() / q[0, mid].sum())
+        g.close()
+    G, ag = np.array(G), np.array(ag)
+    M = len(seeds)
+    z = (G.mean(0) - O.mean(0)) / np.sqrt(G.var(0, ddof=1) / M + O.var(0, ddof=1) / M + 1e-30)
+    assert np.mean(np.abs(z) > 3.5) <= 0.05, z
+    assert np.mean(z ** 2) < 3.0, z
+    assert abs(ag.mean() - ao.mean()) < 4 * math.sqrt(ag.var(ddof=1) / M + ao.var(ddof=1) / M), (ag, ao)
