@@ -64,6 +64,17 @@ struct Scalars {
   int32_t pad2;
 };
 
+constexpr int MAXGRID = 2048;      // largest push grid
+
+// Load balance of the electron push: the slot range and the duration of every
+// block in the last two launches (by step parity).  A launch cuts the store so
+// that each block gets an equal share of the cost the previous launch measured.
+struct PushBal {
+  long long begin[2][MAXGRID + 1];
+  long long dur[2][MAXGRID];
+  int32_t grid[2];
+};
+
 struct Particles {
   int32_t *w;          // packed cell word
   float *off, *vx, *vy, *vz;
@@ -119,6 +130,7 @@ struct Sim {
   float invdlt2, l2emin_s;         // table index t = log2(E) invdlt2 - l2emin_s
   const float *ttot_e;             // [ntab] sum over electron processes of scale_p sigma_p
   unsigned long long *part;        // [grid][ng+1] per-block charge partials
+  PushBal *bal;                    // electron push ranges and durations
   long long *blkcnt;               // [grid] live counts / output offsets of the compaction
   double pnull_pos;                // 1 - exp(-nu_max(O2+) dt_i)
   double dti;

@@ -120,37 +120,52 @@ __device__ __forceinline__ void log_event(const Sim &S, int64_t step, int s, uin
 // the ordered key space [0, next_id[0]) + [0, next_id[1]) + [0, next_id[2]) +
 // [0, next_id[0]) (the last segment: ps = PS_EION, electrons of an
 // electron-impact detachment, whose parent may also have ionised this step).
-struct IdSpace { uint64_t off[NSP + 1]; uint64_t total; };
+// What appends and collisions read of the step-start state: live counts, the
+// parent-key space and the O2(a) switch.  None of it changes while particles
+// move (only the product counters nnew do), so a push block reads it once.
+struct StepCtx { int64_t n[NSP]; uint64_t off[NSP + 1]; uint64_t total; int meta_on, meta_tab; };
 
-__device__ __forceinline__ IdSpace id_space(const Sim &S) {
-  IdSpace r;
+__device__ __forceinline__ StepCtx step_ctx(const Sim &S) {
+  StepCtx r;
   uint64_t t = 0;
-  for (int s = 0; s < NSP; ++s) { r.off[s] = t; t += S.sc->next_id[s]; }
+  for (int s = 0; s < NSP; ++s) { r.n[s] = (int64_t)S.sc->n[s]; r.off[s] = t; t += S.sc->next_id[s]; }
   r.off[PS_EION] = t;
   t += S.sc->next_id[0];
   r.total = t > 0 ? t : 1;
+  r.meta_on = S.sc->meta_on;
+  r.meta_tab = S.sc->meta_tab;
   return r;
 }
 
-__device__ __forceinline__ int64_t append(const Sim &S, int s, int ps, uint32_t pid, const IdSpace &ids) {
-  // one reservation per wave: the active lanes of this call site take consecutive keys
-  const unsigned long long act = __ballot(1);
-  const int lane = __lane_id();
-  const int leader = __ffsll((long long)act) - 1;
-  unsigned long long base = 0ull;
-  if (lane == leader) base = atomicAdd(&S.sc->nnew[s], (unsigned long long)__popcll(act));
-  base = __shfl(base, leader, 64);
-  const unsigned long long k = base + (unsigned long long)__popcll(act & ((1ull << lane) - 1ull));
-  const int64_t slot = (int64_t)S.sc->n[s] + (int64_t)k;
+// rank of this lane among the active lanes act
+__device__ __forceinline__ unsigned long long lane_rank(unsigned long long act) {
+  return (unsigned long long)__popcll(act & ((1ull << __lane_id()) - 1ull));
+}
+
+// product key k of species s from parent (ps, pid): its slot n + k, its parent key
+// and bucket; -1 (and the capacity error) when the store or the key space is full
+__device__ __forceinline__ int64_t place(const Sim &S, const StepCtx &cx, int s, int ps, uint32_t pid,
+                                         unsigned long long k) {
+  const int64_t slot = cx.n[s] + (int64_t)k;
   if (k >= (unsigned long long)S.max_products || slot >= S.cap[s]) {
     atomicOr(&S.sc->err, (uint32_t)E_CAPACITY);
     return -1;
   }
   S.pkey[s][k] = ((uint64_t)ps << 56) | ((uint64_t)pid << 24) | k;
-  const int b = (int)(((ids.off[ps] + pid) * (uint64_t)NBKT) / ids.total);
+  const int b = (int)(((cx.off[ps] + pid) * (uint64_t)NBKT) / cx.total);
   S.pbkt[s][k] = b;
   atomicAdd(&S.bcnt[s * NBKT + b], 1);
   return slot;
+}
+
+// one reservation per wave: the active lanes of this call site take consecutive keys
+__device__ __forceinline__ int64_t append(const Sim &S, const StepCtx &cx, int s, int ps, uint32_t pid) {
+  const unsigned long long act = __ballot(1);
+  const int leader = __ffsll((long long)act) - 1;
+  unsigned long long base = 0ull;
+  if (__lane_id() == leader) base = atomicAdd(&S.sc->nnew[s], (unsigned long long)__popcll(act));
+  base = __shfl(base, leader, 64);
+  return place(S, cx, s, ps, pid, base + lane_rank(act));
 }
 
 __device__ __forceinline__ void put(const Particles &P, int64_t i, int32_t w, float off, float vx, float vy,
@@ -406,11 +421,18 @@ __global__ __launch_bounds__(BS) void k_fixup(Sim S) {
 // out as one partial per block; k_reduce adds the partials into the species
 // histogram, so no global atomics are needed for the bulk of the charge.
 constexpr int GROUP = 8;
-constexpr int MAXGRID = 2048;
 #ifndef PICMCC_CAND_ILP
 #define PICMCC_CAND_ILP 1
 #endif
 constexpr int CAND_ILP = PICMCC_CAND_ILP;   // candidates whose gathers a thread keeps in flight
+#ifndef PICMCC_FFE_SLOTS
+#define PICMCC_FFE_SLOTS 2
+#endif
+// electron slots per lane whose free-flight ends a wave lists before working them
+constexpr int FFE_SLOTS = PICMCC_FFE_SLOTS;
+static_assert(GROUP % FFE_SLOTS == 0, "FFE_SLOTS divides GROUP");
+// outcome flags of a listed free-flight end, in the (zero) cell bits of its new flight
+constexpr uint32_t FFE_CAND = 1u, FFE_REDRAW = 2u;
 
 // energies of particles absorbed at x = 0 / x = L, per block
 struct WallHist { unsigned int iedf[2][NBIN]; };
@@ -428,6 +450,11 @@ struct PushShared {
   float *roff, *rvx, *rvy, *rvz;
   uint32_t *rid;
   unsigned short *rslot;
+  // electrons: free-flight ends of FFE_SLOTS slots per lane, listed per wave (id,
+  // then the outcome word; squared speed, negative for a capped flight)
+  uint32_t *fid;
+  float *fv2;
+  const StepCtx *cx;       // step-start state, in the block's LDS
 };
 
 __device__ __forceinline__ size_t align_up(size_t x) { return (x + 15) & ~(size_t)15; }
@@ -461,9 +488,9 @@ struct DepRun {
 };
 
 // one product of species s from parent (ps, pid)
-__device__ __forceinline__ void emit(const Sim &S, int s, int ps, uint32_t pid, int32_t w, float off, float vx,
-                                     float vy, float vz) {
-  const int64_t slot = append(S, s, ps, pid, id_space(S));
+__device__ __forceinline__ void emit(const Sim &S, const StepCtx &cx, int s, int ps, uint32_t pid, int32_t w,
+                                     float off, float vx, float vy, float vz) {
+  const int64_t slot = append(S, cx, s, ps, pid);
   if (slot >= 0) put(S.p[s], slot, w, off, vx, vy, vz);
 }
 
@@ -541,7 +568,7 @@ __device__ void collide_electron(const Sim &S, int64_t step, const Cand &q, Push
     return;
   }
   atomicAdd(&bc.c[C_EVENT + chosen], 1u);
-  if (S.sc->meta_on && chosen == S.sc->meta_tab) dep_global(S.meta_src, cell, off);   // an O2(a) is born here
+  if (sh.cx->meta_on && chosen == sh.cx->meta_tab) dep_global(S.meta_src, cell, off);   // an O2(a) is born here
   float d0, d1, d2;
   iso_dir(c.z, c.w, d0, d1, d2);
   float enew;
@@ -556,11 +583,24 @@ __device__ void collide_electron(const Sim &S, int64_t step, const Cand &q, Push
     const U4 p1 = draw(S, 0, id, step, P_PROD, 1);
     const float er = e - eth, r = unif(p0.x);
     enew = (1.0f - r) * er;
+    // keys of both products: the two reservations are in flight together
+    const unsigned long long act = __ballot(1);
+    const int leader = __ffsll((long long)act) - 1;
+    unsigned long long be = 0ull, bi = 0ull;
+    if (__lane_id() == leader) {
+      be = atomicAdd(&S.sc->nnew[0], (unsigned long long)__popcll(act));
+      bi = atomicAdd(&S.sc->nnew[1], (unsigned long long)__popcll(act));
+    }
+    be = __shfl(be, leader, 64);
+    bi = __shfl(bi, leader, 64);
+    const StepCtx &cx = *sh.cx;
     {                                          // secondary electron, isotropic, energy r E_r
       float s0, s1, s2;
       iso_dir(p0.y, p0.z, s0, s1, s2);
       const float vm = sqrtf(S.two_e_m[0] * fmaxf(r * er, 0.0f));
-      emit(S, 0, 0, id, cell | (int32_t)new_flight_f(S.inv_nd_ef, p0.w), off, vm * s0, vm * s1, vm * s2);
+      const int64_t slot = place(S, cx, 0, 0, id, be + lane_rank(act));
+      if (slot >= 0)
+        put(S.p[0], slot, cell | (int32_t)new_flight_f(S.inv_nd_ef, p0.w), off, vm * s0, vm * s1, vm * s2);
       dep_lds(sh.Q, cell, off);
       count_lanes(bc, C_BORN + 0);
     }
@@ -569,7 +609,8 @@ __device__ void collide_electron(const Sim &S, int64_t step, const Cand &q, Push
       normals(p1.x, p1.y, z0, z1);
       normals(p1.z, p1.w, z2, z3);
       const float vt = S.vt_gas[1];
-      emit(S, 1, 0, id, cell, off, vt * z0, vt * z1, vt * z2);
+      const int64_t slot = place(S, cx, 1, 0, id, bi + lane_rank(act));
+      if (slot >= 0) put(S.p[1], slot, cell, off, vt * z0, vt * z1, vt * z2);
       dep_global(S.Q + (size_t)(S.ng + 1), cell, off);
       count_lanes(bc, C_BORN + 1);
     }
@@ -579,7 +620,7 @@ __device__ void collide_electron(const Sim &S, int64_t step, const Cand &q, Push
     normals(p1.x, p1.y, z0, z1);
     normals(p1.z, p1.w, z2, z3);
     const float vt = S.vt_gas[2];
-    emit(S, 2, 0, id, cell, off, vt * z0, vt * z1, vt * z2);
+    emit(S, *sh.cx, 2, 0, id, cell, off, vt * z0, vt * z1, vt * z2);
     dep_global(S.Q + (size_t)2 * (S.ng + 1), cell, off);
     count_lanes(bc, C_BORN + 2);
     P.w[i] = W_DEAD;
@@ -628,7 +669,7 @@ __device__ void collide_ion(const Sim &S, int64_t step, const Cand &q, PushShare
     const float g = cl ? sqrtf(pd.inv_mu2 * ec) : sqrtf(g2);
     float dens;
     if (pd.target == T_GRIDPOS) dens = fmaf(off, sh.N[cell + 1] - sh.N[cell], sh.N[cell]) * inv_numax;
-    else if (pd.target == T_O2A && S.sc->meta_on)
+    else if (pd.target == T_O2A && sh.cx->meta_on)
       dens = fmaf(off, S.na_f[cell + 1] - S.na_f[cell], S.na_f[cell]) * inv_numax;
     else dens = pd.scale * (S_ == 2 ? inv_numax : 1.0f);
     const float sg = ec < pd.e_th ? 0.0f : tab_sigma(sh.tab + k * S.ntab, tab_pos(S, ec));
@@ -669,7 +710,7 @@ __device__ void collide_ion(const Sim &S, int64_t step, const Cand &q, PushShare
     float d0, d1, d2;
     iso_dir(p0.y, p0.z, d0, d1, d2);
     const float vm = sqrtf(S.two_e_m[0] * fmaxf(erel_c - eth_c, 0.0f));
-    emit(S, 0, S_, id, cell | (int32_t)new_flight_f(S.inv_nd_ef, p0.w), off, vm * d0, vm * d1, vm * d2);
+    emit(S, *sh.cx, 0, S_, id, cell | (int32_t)new_flight_f(S.inv_nd_ef, p0.w), off, vm * d0, vm * d1, vm * d2);
     dep_global(S.Q, cell, off);
     count_lanes(bc, C_BORN + 0);
     P.w[i] = W_DEAD;
@@ -689,6 +730,7 @@ struct PushLds {
   int qn[16];              // queued candidates of each wave in the current pass
   BlockCounts bc;
   WallHist wall;
+  StepCtx cx;
 };
 
 // Push of the slots [begin, end) of species S_ by one block (begin a multiple of
@@ -709,6 +751,8 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
   sh.tab = (float *)(smem + o); o = align_up(o + sizeof(float) * np * S.ntab);
   sh.ttot = (float *)(smem + o); if (S_ == 0) o = align_up(o + sizeof(float) * S.ntab);
   sh.queue = (unsigned short *)(smem + o); o = align_up(o + sizeof(unsigned short) * GROUP * BS);
+  sh.fid = (uint32_t *)(smem + o); if (S_ == 0) o += sizeof(uint32_t) * FFE_SLOTS * BS;
+  sh.fv2 = (float *)(smem + o); if (S_ == 0) o += sizeof(float) * FFE_SLOTS * BS;
   const int rq_cap = S_ == 0 ? S.rq_cap : 0;
   sh.rw = (int32_t *)(smem + o); o += 4 * (size_t)rq_cap;
   sh.roff = (float *)(smem + o); o += 4 * (size_t)rq_cap;
@@ -729,6 +773,8 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
     for (int j = threadIdx.x; j < S.ntab; j += BS) sh.ttot[j] = S.ttot_e[j];
   for (int k = threadIdx.x; k < NCOUNT; k += BS) bc.c[k] = 0u;
   if (threadIdx.x < 16) qn[threadIdx.x] = 0;
+  if (threadIdx.x == 0) pl.cx = step_ctx(S);
+  sh.cx = &pl.cx;
   float inv_numax = 0.0f;
   double pnull = 0.0;
   if (S_ == 1) pnull = S.pnull_pos;
@@ -739,24 +785,211 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
   const float qmdt = S.qmdt[S_], dtdx = S.dtdx[S_];
   const bool nocoll = (S.flags & F_NO_COLL) != 0;
   const int lane = threadIdx.x & 63;
-  // Electrons: each wave queues the collision candidates of its own GROUP * 64 slots
-  // of a pass (their state as LDS records while the wave's share lasts) and works
-  // them off itself, so the waves of a block never wait for each other inside a run.
-  // Ions: one queue per block, worked off by all its lanes between two barriers.
+  // Electrons: each wave lists the free-flight ends of FFE_SLOTS slots per lane and
+  // works the list on full lanes (draw, next flight, rate bound), then queues the
+  // collision candidates of its own GROUP * 64 slots of a pass (their state as LDS
+  // records while the wave's share lasts) and works them off itself, so the waves
+  // of a block never wait for each other inside a run.  Ions: one queue per block,
+  // worked off by all its lanes between two barriers.
   const int wv = threadIdx.x >> 6;
-  int *wcnt = &qn[wv];
   unsigned short *wq = sh.queue + wv * GROUP * 64;
   const int rqw = rq_cap / (BS / 64), r0 = wv * rqw;
   ThreadCounts tc;
   DepRun run;
+  if constexpr (S_ == 0) {
+    const unsigned long long below = (1ull << lane) - 1ull;
+    uint32_t *fid = sh.fid + wv * FFE_SLOTS * 64;
+    float *fv2 = sh.fv2 + wv * FFE_SLOTS * 64;
+    // one wave's pass over the 512 slots from ub (wave-uniform)
+    auto pass = [&](const int64_t ub) __attribute__((always_inline)) {
+      const int64_t i0 = ub + (int64_t)GROUP * lane;
+      const int nv = i0 < end ? (int)min((int64_t)GROUP, end - i0) : 0;
+      int32_t w[GROUP];
+      float off[GROUP], vx[GROUP], vy[GROUP], vz[GROUP];
+      uint32_t id[GROUP];
+      if (nv > 0) {
+        // every cache line of the cold fields is needed anyway (a third of the
+        // electrons end a free flight each step), so they stream in with the hot ones
+        const int4 wa = *reinterpret_cast<const int4 *>(P.w + i0), wb = *reinterpret_cast<const int4 *>(P.w + i0 + 4);
+        const float4 oa = *reinterpret_cast<const float4 *>(P.off + i0), ob = *reinterpret_cast<const float4 *>(P.off + i0 + 4);
+        const float4 va = *reinterpret_cast<const float4 *>(P.vx + i0), vb = *reinterpret_cast<const float4 *>(P.vx + i0 + 4);
+        const uint4 ia = *reinterpret_cast<const uint4 *>(P.id + i0), ib = *reinterpret_cast<const uint4 *>(P.id + i0 + 4);
+        const float4 ya = *reinterpret_cast<const float4 *>(P.vy + i0), yb = *reinterpret_cast<const float4 *>(P.vy + i0 + 4);
+        const float4 za = *reinterpret_cast<const float4 *>(P.vz + i0), zb = *reinterpret_cast<const float4 *>(P.vz + i0 + 4);
+        w[0] = wa.x; w[1] = wa.y; w[2] = wa.z; w[3] = wa.w; w[4] = wb.x; w[5] = wb.y; w[6] = wb.z; w[7] = wb.w;
+        off[0] = oa.x; off[1] = oa.y; off[2] = oa.z; off[3] = oa.w; off[4] = ob.x; off[5] = ob.y; off[6] = ob.z; off[7] = ob.w;
+        vx[0] = va.x; vx[1] = va.y; vx[2] = va.z; vx[3] = va.w; vx[4] = vb.x; vx[5] = vb.y; vx[6] = vb.z; vx[7] = vb.w;
+        id[0] = ia.x; id[1] = ia.y; id[2] = ia.z; id[3] = ia.w; id[4] = ib.x; id[5] = ib.y; id[6] = ib.z; id[7] = ib.w;
+        vy[0] = ya.x; vy[1] = ya.y; vy[2] = ya.z; vy[3] = ya.w; vy[4] = yb.x; vy[5] = yb.y; vy[6] = yb.z; vy[7] = yb.w;
+        vz[0] = za.x; vz[1] = za.y; vz[2] = za.z; vz[3] = za.w; vz[4] = zb.x; vz[5] = zb.y; vz[6] = zb.z; vz[7] = zb.w;
+      } else {
+#pragma unroll
+        for (int k = 0; k < GROUP; ++k) { w[k] = W_DEAD; off[k] = vx[k] = vy[k] = vz[k] = 0.0f; id[k] = 0u; }
+      }
+      int nq = 0;                                  // candidates this wave queued in this pass
+#pragma unroll
+      for (int k0 = 0; k0 < GROUP; k0 += FFE_SLOTS) {
+        // push FFE_SLOTS slots; list the ones whose free flight ends
+        unsigned int ended = 0u;
+        int nf = 0;
+#pragma unroll
+        for (int k = k0; k < k0 + FFE_SLOTS; ++k) {
+          bool fe = false;
+          if (k < nv && w[k] >= 0) {
+            ++tc.push;
+            const int cell = w[k] & (int32_t)W_CELL;
+            // gather (linear weighting), leapfrog velocity then position
+            const float e0 = sh.E[cell], e1 = sh.E[cell + 1];
+            const float v = fmaf(qmdt, fmaf(off[k], e1 - e0, e0), vx[k]);
+            const float xn = fmaf(v, dtdx, off[k]);
+            vx[k] = v;
+            if (!(fabsf(xn) < 1.0e9f)) {
+              atomicOr(&S.sc->err, (uint32_t)E_NAN);
+              w[k] = W_DEAD;
+            } else {
+              const float fl = floorf(xn);
+              int nc = cell + (int)fl;
+              float no = xn - fl;
+              if (no >= 1.0f) { nc += 1; no -= 1.0f; }
+              off[k] = no;
+              if (nc < 0 || nc >= ng) {                // absorbed by an electrode
+                const int side = nc < 0 ? 0 : 1;
+                const float en = S.half_m_e[0] * (v * v + vy[k] * vy[k] + vz[k] * vz[k]);
+                atomicAdd(&wall.iedf[side][ebin(en)], 1u);
+                atomicAdd(&bc.c[(side ? C_ABSL : C_ABS0) + 0], 1u);
+                w[k] = W_DEAD;
+                if (S.event_cap > 0) log_event(S, step, 0, id[k], -3);
+              } else {
+                const int cd = w[k] >> W_CD_SHIFT;
+                const int cdn = nocoll ? cd : cd - 1;
+                if (cdn > 0 || nocoll) {
+                  w[k] = nc | (w[k] & (int32_t)W_CAP) | (cdn << W_CD_SHIFT);
+                  run.add(sh.Q, nc, no);
+                } else {                               // the free flight ends: listed
+                  w[k] = nc | (w[k] & (int32_t)W_CAP);
+                  fe = true;
+                }
+              }
+            }
+          }
+          const unsigned long long m = __ballot(fe);
+          if (fe) {
+            const int e = nf + __popcll(m & below);
+            fid[e] = id[k];
+            fv2[e] = (w[k] & (int32_t)W_CAP) ? -1.0f : vx[k] * vx[k] + vy[k] * vy[k] + vz[k] * vz[k];
+          }
+          nf += __popcll(m);
+          ended |= (fe ? 1u : 0u) << (k - k0);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // the listed ends on full lanes: next flight, and the early null test
+        // against the summed rate table (the channel is chosen after the pass)
+        for (int e = lane; e < nf; e += 64) {
+          const uint32_t pid = fid[e];
+          const float v2 = fv2[e];
+          const U4 c = draw(S, 0, pid, step, P_CAND, 0);
+          uint32_t r = new_flight_f(S.inv_nd_ef, c.x);
+          if (v2 < 0.0f) {                           // end of a capped flight: no collision
+            r |= FFE_REDRAW;
+            count_lanes(bc, C_REDRAW);
+          } else {
+            ++tc.cand;
+            const ECand en = electron_energy(S, v2);
+            if (en.clamped) count_lanes(bc, C_CLAMP);
+            const TabPos tp = tab_pos(S, en.ec);
+            if (unif(c.y) < electron_bound(sh, tp, en.g) * 1.000001f) r |= FFE_CAND;
+          }
+          fid[e] = r;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        // outcomes back to the slots: null collisions deposit, candidates are queued
+        int f = 0;
+#pragma unroll
+        for (int k = k0; k < k0 + FFE_SLOTS; ++k) {
+          const bool fe = (ended >> (k - k0)) & 1u;
+          const unsigned long long m = __ballot(fe);
+          bool cand = false;
+          if (fe) {
+            const uint32_t r = fid[f + __popcll(m & below)];
+            const int cell = w[k] & (int32_t)W_CELL;
+            w[k] = cell | (int32_t)(r & ~W_CELL);
+            if (r & FFE_CAND) {
+              cand = true;
+            } else {
+              run.add(sh.Q, cell, off[k]);
+              if (r & FFE_REDRAW) {
+                if (S.event_cap > 0) log_event(S, step, 0, id[k], -2);
+              } else {
+                ++tc.nul;
+                if (S.event_cap > 0) log_event(S, step, 0, id[k], -1);
+              }
+            }
+          }
+          f += __popcll(m);
+          const unsigned long long mc = __ballot(cand);
+          if (cand) {
+            const int e = nq + __popcll(mc & below);
+            const unsigned short slot = (unsigned short)(i0 - ub + k);
+            if (e < rqw) {
+              const int r = r0 + e;
+              sh.rw[r] = w[k]; sh.roff[r] = off[k]; sh.rvx[r] = vx[k]; sh.rvy[r] = vy[k]; sh.rvz[r] = vz[k];
+              sh.rid[r] = id[k]; sh.rslot[r] = slot;
+            } else {
+              wq[e - rqw] = slot;
+            }
+          }
+          nq += __popcll(mc);
+        }
+        // the outcome list is read: the next slots may list theirs
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      }
+      if (nv == GROUP) {
+        *reinterpret_cast<int4 *>(P.w + i0) = make_int4(w[0], w[1], w[2], w[3]);
+        *reinterpret_cast<int4 *>(P.w + i0 + 4) = make_int4(w[4], w[5], w[6], w[7]);
+        *reinterpret_cast<float4 *>(P.off + i0) = make_float4(off[0], off[1], off[2], off[3]);
+        *reinterpret_cast<float4 *>(P.off + i0 + 4) = make_float4(off[4], off[5], off[6], off[7]);
+        *reinterpret_cast<float4 *>(P.vx + i0) = make_float4(vx[0], vx[1], vx[2], vx[3]);
+        *reinterpret_cast<float4 *>(P.vx + i0 + 4) = make_float4(vx[4], vx[5], vx[6], vx[7]);
+      } else {
+        for (int k = 0; k < nv; ++k) { P.w[i0 + k] = w[k]; P.off[i0 + k] = off[k]; P.vx[i0 + k] = vx[k]; }
+      }
+      // the wave's queue is complete: its LDS and global writes are visible to its lanes
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+      for (int e = lane; e < nq; e += 64) {
+        Cand c;
+        if (e < rqw) {
+          const int r = r0 + e;
+          c.i = ub + sh.rslot[r]; c.w = sh.rw[r]; c.id = sh.rid[r]; c.off = sh.roff[r];
+          c.vx = sh.rvx[r]; c.vy = sh.rvy[r]; c.vz = sh.rvz[r];
+        } else {
+          c = load_cand(P, ub + wq[e - rqw]);
+        }
+        collide_electron(S, step, c, sh, bc, tc);
+      }
+      // every lane has read its entries: the next pass may overwrite them
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    };
+    for (int64_t base = begin; base < end; base += (int64_t)GROUP * BS)
+      if (base + (int64_t)wv * GROUP * 64 < end) pass(base + (int64_t)wv * GROUP * 64);
+  } else {
   int par = 0;
   for (int64_t base = begin; base < end; base += (int64_t)GROUP * BS, par ^= 1) {
     const int64_t i0 = base + (int64_t)GROUP * threadIdx.x;
-    unsigned int cmask = 0u;               // ion candidates of this thread (electrons queue directly)
+    unsigned int cmask = 0u;               // candidates of this thread
     if (i0 < end) {
       const int nv = (int)min((int64_t)GROUP, end - i0);
       int32_t w[GROUP];
-      float off[GROUP], vx[GROUP], vy[GROUP], vz[GROUP];
+      float off[GROUP], vx[GROUP];
       uint32_t id[GROUP];
       {
         const int4 wa = *reinterpret_cast<const int4 *>(P.w + i0), wb = *reinterpret_cast<const int4 *>(P.w + i0 + 4);
@@ -765,17 +998,9 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
         w[0] = wa.x; w[1] = wa.y; w[2] = wa.z; w[3] = wa.w; w[4] = wb.x; w[5] = wb.y; w[6] = wb.z; w[7] = wb.w;
         off[0] = oa.x; off[1] = oa.y; off[2] = oa.z; off[3] = oa.w; off[4] = ob.x; off[5] = ob.y; off[6] = ob.z; off[7] = ob.w;
         vx[0] = va.x; vx[1] = va.y; vx[2] = va.z; vx[3] = va.w; vx[4] = vb.x; vx[5] = vb.y; vx[6] = vb.z; vx[7] = vb.w;
-        if (S_ == 0 || (!nocoll && pnull > 0.0)) {
+        if (!nocoll && pnull > 0.0) {
           const uint4 ia = *reinterpret_cast<const uint4 *>(P.id + i0), ib = *reinterpret_cast<const uint4 *>(P.id + i0 + 4);
           id[0] = ia.x; id[1] = ia.y; id[2] = ia.z; id[3] = ia.w; id[4] = ib.x; id[5] = ib.y; id[6] = ib.z; id[7] = ib.w;
-        }
-        if (S_ == 0) {
-          // electrons: every cache line of the cold fields is needed anyway (a third of the
-          // particles end a free flight each step), so they stream in with the hot ones
-          const float4 ya = *reinterpret_cast<const float4 *>(P.vy + i0), yb = *reinterpret_cast<const float4 *>(P.vy + i0 + 4);
-          const float4 za = *reinterpret_cast<const float4 *>(P.vz + i0), zb = *reinterpret_cast<const float4 *>(P.vz + i0 + 4);
-          vy[0] = ya.x; vy[1] = ya.y; vy[2] = ya.z; vy[3] = ya.w; vy[4] = yb.x; vy[5] = yb.y; vy[6] = yb.z; vy[7] = yb.w;
-          vz[0] = za.x; vz[1] = za.y; vz[2] = za.z; vz[3] = za.w; vz[4] = zb.x; vz[5] = zb.y; vz[6] = zb.z; vz[7] = zb.w;
         }
       }
 #pragma unroll
@@ -800,7 +1025,7 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
         off[k] = no;
         if (nc < 0 || nc >= ng) {                      // absorbed by an electrode
           const int side = nc < 0 ? 0 : 1;
-          const float uy = S_ == 0 ? vy[k] : P.vy[i0 + k], uz = S_ == 0 ? vz[k] : P.vz[i0 + k];
+          const float uy = P.vy[i0 + k], uz = P.vz[i0 + k];
           const float en = S.half_m_e[S_] * (v * v + uy * uy + uz * uz);
           atomicAdd(&wall.iedf[side][ebin(en)], 1u);
           atomicAdd(&bc.c[(side ? C_ABSL : C_ABS0) + S_], 1u);
@@ -808,50 +1033,11 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
           if (S.event_cap > 0) log_event(S, step, S_, P.id[i0 + k], -3);
           continue;
         }
-        if (S_ == 0) {
-          const int cd = w[k] >> W_CD_SHIFT;
-          const int cdn = nocoll ? cd : cd - 1;
-          if (cdn > 0 || nocoll) {
-            w[k] = nc | (w[k] & (int32_t)W_CAP) | (cdn << W_CD_SHIFT);
-            run.add(sh.Q, nc, no);
-          } else {                                     // the free flight ends: draw the next one
-            const U4 c = draw(S, 0, id[k], step, P_CAND, 0);
-            const bool capped = (w[k] & (int32_t)W_CAP) != 0;
-            w[k] = nc | (int32_t)new_flight_f(S.inv_nd_ef, c.x);
-            if (capped) {                              // end of a capped flight: no collision
-              run.add(sh.Q, nc, no);
-              count_lanes(bc, C_REDRAW);
-              if (S.event_cap > 0) log_event(S, step, 0, id[k], -2);
-            } else {
-              ++tc.cand;
-              const ECand en = electron_energy(S, v * v + vy[k] * vy[k] + vz[k] * vz[k]);
-              if (en.clamped) count_lanes(bc, C_CLAMP);
-              const TabPos tp = tab_pos(S, en.ec);
-              if (unif(c.y) < electron_bound(sh, tp, en.g) * 1.000001f) {
-                // may collide: the channel is chosen by the block after the pass
-                const int e = atomicAdd(wcnt, 1);
-                const unsigned short slot = (unsigned short)(i0 - base + k);
-                if (e < rqw) {
-                  const int r = r0 + e;
-                  sh.rw[r] = w[k]; sh.roff[r] = no; sh.rvx[r] = v; sh.rvy[r] = vy[k]; sh.rvz[r] = vz[k];
-                  sh.rid[r] = id[k]; sh.rslot[r] = slot;
-                } else {
-                  wq[e - rqw] = slot;
-                }
-              } else {                                 // null collision
-                run.add(sh.Q, nc, no);
-                ++tc.nul;
-                if (S.event_cap > 0) log_event(S, step, 0, id[k], -1);
-              }
-            }
-          }
-        } else {
-          w[k] = nc;
-          bool cand = false;
-          if (!nocoll && pnull > 0.0) cand = (double)unif(draw(S, S_, id[k], step, P_CAND, 0).x) < pnull;
-          if (cand) cmask |= 1u << k;
-          else run.add(sh.Q, nc, no);
-        }
+        w[k] = nc;
+        bool cand = false;
+        if (!nocoll && pnull > 0.0) cand = (double)unif(draw(S, S_, id[k], step, P_CAND, 0).x) < pnull;
+        if (cand) cmask |= 1u << k;
+        else run.add(sh.Q, nc, no);
       }
       if (nv == GROUP) {
         *reinterpret_cast<int4 *>(P.w + i0) = make_int4(w[0], w[1], w[2], w[3]);
@@ -864,58 +1050,32 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
         for (int k = 0; k < nv; ++k) { P.w[i0 + k] = w[k]; P.off[i0 + k] = off[k]; P.vx[i0 + k] = vx[k]; }
       }
     }
-    if (S_ == 0) {
-      // the wave's queue is complete: its LDS and global writes are visible to its lanes
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      const int nq = *wcnt;
-      for (int e = lane; e < nq; e += 64) {
-        Cand c;
-        if (e < rqw) {
-          const int r = r0 + e;
-          c.i = base + sh.rslot[r]; c.w = sh.rw[r]; c.id = sh.rid[r]; c.off = sh.roff[r];
-          c.vx = sh.rvx[r]; c.vy = sh.rvy[r]; c.vz = sh.rvz[r];
-        } else {
-          c = load_cand(P, base + wq[e - rqw]);
-        }
-        collide_electron(S, step, c, sh, bc, tc);
-      }
-      // every lane has read the count and its entries: reset for the next pass
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-      if (lane == 0) *wcnt = 0;
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
-    } else {
-      // queue the candidates: one LDS atomic per wave
-      const int mine = __popc(cmask);
-      const int incl = wave_incl_scan(mine);
-      int wbase = 0;
-      if (lane == 63 && incl > 0) wbase = atomicAdd(&qn[par], incl);
-      wbase = __shfl(wbase, 63, 64);
-      int q = wbase + incl - mine;
-      for (unsigned int m = cmask; m; m &= m - 1) sh.queue[q++] = (unsigned short)(i0 - base + __ffs(m) - 1);
-      __syncthreads();
-      const int nq = qn[par];
-      if (threadIdx.x == 0) qn[par ^ 1] = 0;   // counter of the next pass, unused since the last barrier
-      for (int k = threadIdx.x; k < nq; k += CAND_ILP * BS) {
-        // gathers of up to CAND_ILP candidates in flight together
-        Cand c[CAND_ILP];
-        bool h[CAND_ILP];
+    // queue the candidates: one LDS atomic per wave
+    const int mine = __popc(cmask);
+    const int incl = wave_incl_scan(mine);
+    int wbase = 0;
+    if (lane == 63 && incl > 0) wbase = atomicAdd(&qn[par], incl);
+    wbase = __shfl(wbase, 63, 64);
+    int q = wbase + incl - mine;
+    for (unsigned int m = cmask; m; m &= m - 1) sh.queue[q++] = (unsigned short)(i0 - base + __ffs(m) - 1);
+    __syncthreads();
+    const int nq = qn[par];
+    if (threadIdx.x == 0) qn[par ^ 1] = 0;   // counter of the next pass, unused since the last barrier
+    for (int k = threadIdx.x; k < nq; k += CAND_ILP * BS) {
+      // gathers of up to CAND_ILP candidates in flight together
+      Cand c[CAND_ILP];
+      bool h[CAND_ILP];
 #pragma unroll
-        for (int u = 0; u < CAND_ILP; ++u) {
-          h[u] = k + u * BS < nq;
-          if (h[u]) c[u] = load_cand(P, base + sh.queue[k + u * BS]);
-        }
-#pragma unroll
-        for (int u = 0; u < CAND_ILP; ++u)
-          if (h[u]) collide_ion<S_>(S, step, c[u], sh, bc, tc, inv_numax);
+      for (int u = 0; u < CAND_ILP; ++u) {
+        h[u] = k + u * BS < nq;
+        if (h[u]) c[u] = load_cand(P, base + sh.queue[k + u * BS]);
       }
-      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < CAND_ILP; ++u)
+        if (h[u]) collide_ion<S_>(S, step, c[u], sh, bc, tc, inv_numax);
     }
+    __syncthreads();
+  }
   }
   __syncthreads();
   run.flush(sh.Q);
@@ -932,12 +1092,82 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
   __syncthreads();   // the LDS may be set up for the next run
 }
 
-// one discharge: block b pushes the b-th contiguous chunk of the store
+// Slot range [range[0], range[1]) of this block in an electron push over n slots,
+// worked out by one wave.  The previous launch (other step parity) left a cost
+// map: its block j spent dur[j] on the slots [begin[j], begin[j + 1]).  The cut
+// points are where the cumulative cost reaches equal fractions, rounded to 512
+// slots; without a map of this grid the store is cut into equal chunks.
+__device__ void balanced_range(const PushBal *B, int par, int64_t n, long long *range) {
+  const int G = gridDim.x, b = blockIdx.x, lane = threadIdx.x & 63, prv = par ^ 1;
+  long long cut[2];
+  if (B->grid[prv] != G) {
+    const int64_t chunk = push_chunk(n, G);
+    cut[0] = min(n, (int64_t)b * chunk);
+    cut[1] = min(n, cut[0] + chunk);
+  } else {
+    // each lane sums a contiguous segment of the blocks' durations; a wave scan
+    // gives the cumulative cost at each segment start
+    const int per = (G + 63) / 64, j0 = min(G, lane * per), j1 = min(G, j0 + per);
+    double own = 0.0;
+    for (int j = j0; j < j1; ++j) own += (double)B->dur[prv][j];
+    const double incl = wave_incl_scan(own);
+    const double total = __shfl(incl, 63, 64);
+    const double before = incl - own;
+    for (int e = 0; e < 2; ++e) {
+      const double c = total * (double)(b + e) / (double)G;
+      double pos = -1.0;                     // slot where the cumulative cost reaches c
+      if (b + e == G) {
+        pos = (double)n;
+      } else if (c >= before && c < incl) {
+        double acc = before;
+        for (int j = j0; j < j1; ++j) {
+          const double d = (double)B->dur[prv][j];
+          if (c < acc + d) {
+            const double lo = (double)B->begin[prv][j], hi = (double)B->begin[prv][j + 1];
+            pos = lo + (c - acc) / d * (hi - lo);
+            break;
+          }
+          acc += d;
+        }
+      }
+      // the one lane that found it hands it to the wave
+      const unsigned long long m = __ballot(pos >= 0.0);
+      const int src = m ? __ffsll((long long)m) - 1 : 0;
+      pos = __shfl(pos, src, 64);
+      long long x = m ? (long long)pos : (long long)n;
+      x = x / (GROUP * 64) * (GROUP * 64);
+      cut[e] = (b + e == G) ? (long long)n : min((long long)n, max(0ll, x));
+    }
+  }
+  if (lane == 0) { range[0] = cut[0]; range[1] = max(cut[0], cut[1]); }
+}
+
+// one discharge: electrons in ranges balanced by the previous launch's cost,
+// ions by block b pushing the b-th contiguous chunk of the store
 template <int BS, int S_>
 __global__ __launch_bounds__(BS, PICMCC_PUSH_WAVES) void k_push(Sim S, int64_t step) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ PushLds pl;
   const int64_t N = (int64_t)S.sc->n[S_];
+  if (S_ == 0) {           // every block writes its partial row, also for an empty range
+    __shared__ long long range[2];
+    const long long t0 = (long long)__builtin_amdgcn_s_memrealtime();
+    const int par = (int)(step & 1);
+    if (threadIdx.x < 64) balanced_range(S.bal, par, N, range);
+    __syncthreads();
+    const int64_t begin = range[0], end = range[1];
+    push_run<BS, S_>(S, step, begin, end, S.part + (size_t)blockIdx.x * (S.ng + 1), smem, pl);
+    if (threadIdx.x == 0) {
+      const long long t1 = (long long)__builtin_amdgcn_s_memrealtime();
+      S.bal->begin[par][blockIdx.x] = begin;
+      S.bal->dur[par][blockIdx.x] = max(1ll, t1 - t0);
+      if (blockIdx.x == gridDim.x - 1) {
+        S.bal->begin[par][gridDim.x] = end;
+        S.bal->grid[par] = (int32_t)gridDim.x;
+      }
+    }
+    return;
+  }
   const int64_t chunk = push_chunk(N, gridDim.x);
   const int64_t begin = (int64_t)blockIdx.x * chunk;
   const int64_t end = min(N, begin + chunk);
@@ -945,7 +1175,8 @@ __global__ __launch_bounds__(BS, PICMCC_PUSH_WAVES) void k_push(Sim S, int64_t s
   push_run<BS, S_>(S, step, begin, end, S.part + (size_t)blockIdx.x * (S.ng + 1), smem, pl);
 }
 
-// Q[s] += sum of the partial histograms of the blocks that had particles
+// Q[s] += sum of the partial histograms of the blocks that had particles (for
+// electrons every block of the push writes one)
 template <int BS>
 __global__ __launch_bounds__(BS) void k_reduce(Sim S, int s, int push_grid) {
   const int nn = S.ng + 1;
@@ -953,7 +1184,7 @@ __global__ __launch_bounds__(BS) void k_reduce(Sim S, int s, int push_grid) {
   if (j >= nn) return;
   const int64_t N = (int64_t)S.sc->n[s];
   const int64_t chunk = push_chunk(N, push_grid);
-  const int used = chunk > 0 ? (int)((N + chunk - 1) / chunk) : 0;
+  const int used = s == 0 ? push_grid : chunk > 0 ? (int)((N + chunk - 1) / chunk) : 0;
   unsigned long long sum = 0ull;
   for (int b = blockIdx.y; b < used; b += gridDim.y) sum += S.part[(size_t)b * nn + j];
   if (sum) atomicAdd(&S.Q[(size_t)s * nn + j], sum);
@@ -1192,7 +1423,8 @@ __device__ void eion_run(const Sim &S, int64_t step, int bx, int gx) {
       P.vx[i] = vn * d0; P.vy[i] = vn * d1; P.vz[i] = vn * d2;
       iso_dir(p0.y, p0.z, s0, s1, s2);
       const float vm = sqrtf(S.two_e_m[0] * (r * er));
-      emit(S, 0, PS_EION, id, cell | (int32_t)new_flight_f(S.inv_nd_ef, p0.w), off, vm * s0, vm * s1, vm * s2);
+      emit(S, step_ctx(S), 0, PS_EION, id, cell | (int32_t)new_flight_f(S.inv_nd_ef, p0.w), off, vm * s0, vm * s1,
+           vm * s2);
       dep_global(S.Q, cell, off);
       atomicAdd(&S.sc->cnt[C_BORN + 0], 1ull);
       atomicAdd(&S.kleft_neg[cell], 1);
@@ -1758,6 +1990,7 @@ size_t push_lds_bytes(const Sim &S, int s, int bs) {
   o = (o + 4 * (size_t)S.nproc_sp[s] * S.ntab + 15) & ~(size_t)15;
   if (s == 0) o = (o + 4 * (size_t)S.ntab + 15) & ~(size_t)15;
   o = (o + sizeof(unsigned short) * GROUP * (size_t)bs + 15) & ~(size_t)15;
+  if (s == 0) o += 8 * (size_t)FFE_SLOTS * bs;     // free-flight-end lists: id and squared speed
   if (s == 0) o += 26 * (size_t)S.rq_cap;          // candidate records: 6 words + a 16-bit slot
   return o;
 }

@@ -66,7 +66,7 @@ struct Layout {
   size_t pkey[NSP], pbkt[NSP], ptmp[NSP], bcnt;
   size_t Q, E, phi, sumQ, sumphi, esum, ecnt, edf, iedf, nacc, kleft, cmin, sortcnt, sortbase, sc, sigma,
       hbound, events, partials, ttot, blkcnt, prof, jsum, jcnt, jpow, kleft_neg, dens_ei, meta_src, na, na_f,
-      meta_tmp;
+      meta_tmp, bal;
   size_t take(size_t bytes) {
     const size_t o = total;
     total += (bytes + 255) & ~(size_t)255;
@@ -105,6 +105,7 @@ Layout make_layout(const pic_config &c, const pic_species *sp, int nproc) {
   L.hbound = L.take(8 * (size_t)nproc * (c.table_n - 1));
   L.events = L.take(32 * (size_t)c.event_capacity);
   L.partials = L.take(8 * nn * (size_t)(c.grid > 0 ? c.grid : max_push_grid()));
+  L.bal = L.take(sizeof(PushBal));
   L.ttot = L.take(4 * (size_t)c.table_n);
   L.blkcnt = L.take(8 * 4096);
   L.prof = L.take((8 + 4) * NSP * (size_t)c.ng);   // warm-start loading: per-cell cumulative counts, speeds
@@ -447,6 +448,7 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
   S.hbound = (const double *)(ws + L.hbound);
   S.events = (long long *)(ws + L.events);
   S.part = (unsigned long long *)(ws + L.partials);
+  S.bal = (PushBal *)(ws + L.bal);
   S.ttot_e = (const float *)(ws + L.ttot);
   S.blkcnt = (long long *)(ws + L.blkcnt);
   S.spc = c.steps_per_cycle;
@@ -456,11 +458,11 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
 
   // launch shapes.  The electron push keeps the state of its first candidates of
   // each pass in LDS; give it what the resident blocks (at most 1024 threads per
-  // CU at the push kernels' 128 registers) leave free, beside 3 KB of static LDS.
+  // CU at the push kernels' 128 registers) leave free, beside at most 4 KB of static LDS.
   const size_t lds_cu = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor : prop.sharedMemPerBlock;
   {
     S.rq_cap = 0;
-    const size_t base = push_lds_bytes(S, 0, h->block) + 3072;
+    const size_t base = push_lds_bytes(S, 0, h->block) + 4096;
     const size_t per_cu = std::max<size_t>(1, std::min<size_t>(lds_cu / base, 1024 / h->block));
     const size_t budget = std::min<size_t>(lds_cu / per_cu, prop.sharedMemPerBlock);
     S.rq_cap = budget > base ? (int)(std::min<size_t>(1024, (budget - base) / 26) & ~(size_t)3) : 0;
