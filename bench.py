@@ -23,9 +23,22 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 BYTES_PUSH = 24          # read + write cell word, offset, vx
-BYTES_CAND = 20          # read id, vy, vz; write vy, vz at a free-flight end
+BYTES_CAND = 12          # read id, vy, vz at the end of a free flight (the energy for the null test)
+BYTES_REDRAW = 4         # read id at the end of a capped flight (a new flight only)
+BYTES_SCATTER = 8        # write vy, vz after an electron collision that changes the velocity
 BYTES_PRODUCT = 24       # one new particle record
 HBM_PEAK_GBS = 8000.0    # MI355X HBM3E
+
+
+def push_alg_bytes(dc, procs):
+    """Algorithmic HBM bytes of the electron push over a counter difference dc: the
+    least any electron push with this MCC has to move (the per-unit figures above)."""
+    from paper_0705_0497_amd import binding as B
+    ev = lambda kinds: sum(int(dc[B.C_EVENT + i]) for i, p in enumerate(procs)
+                           if p.species == 0 and p.kind in kinds)
+    born = 2 * ev(("ionize",)) + ev(("attach",))           # products written by the electron kernel
+    return (BYTES_PUSH * int(dc[B.C_PUSH]) + BYTES_CAND * int(dc[B.C_CAND]) + BYTES_REDRAW * int(dc[B.C_REDRAW])
+            + BYTES_SCATTER * ev(("elastic", "excite", "ionize")) + BYTES_PRODUCT * born)
 
 
 def log(*a):
@@ -136,11 +149,7 @@ def main():
     pushes = int(dc[C_PUSH:C_PUSH + 3].sum())
     value = pushes / elapsed
     launches = args.steps * spc
-    kinds = [p.kind for p in procs]
-    ev = lambda k: sum(int(dc[C_EVENT + i]) for i, kk in enumerate(kinds) if kk == k)
-    born_in_push = 2 * ev("ionize") + ev("attach")         # products written by the electron kernel
-    alg_bytes = (BYTES_PUSH * int(dc[C_PUSH]) + BYTES_CAND * int(dc[C_CAND] + dc[C_REDRAW])
-                 + BYTES_PRODUCT * born_in_push)
+    alg_bytes = push_alg_bytes(dc, procs)
     per_launch = alg_bytes / launches
     mean_ms = ms_push / launches
     achieved = per_launch / (mean_ms * 1e-3) / 1e9
@@ -229,11 +238,7 @@ def sweep(args):
     end_counts = [sum(g.count(s) for s in range(3)) for g in members]
     pushes = sum(int(x[B.C_PUSH:B.C_PUSH + 3].sum()) for x in dc)
     push_e = sum(int(x[B.C_PUSH]) for x in dc)
-    cand = sum(int(x[B.C_CAND] + x[B.C_REDRAW]) for x in dc)
-    kinds = [p.kind for p in procs]
-    born = sum(2 * sum(int(x[B.C_EVENT + i]) for i, k in enumerate(kinds) if k == "ionize") +
-               sum(int(x[B.C_EVENT + i]) for i, k in enumerate(kinds) if k == "attach") for x in dc)
-    alg = BYTES_PUSH * push_e + BYTES_CAND * cand + BYTES_PRODUCT * born
+    alg = sum(push_alg_bytes(x, procs) for x in dc)
     achieved = alg / elapsed / 1e9
     cfg = b.config()
     out = {
