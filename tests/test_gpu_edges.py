@@ -74,3 +74,24 @@ def test_few_particles_per_species(n):
     st, nid, sidx = H.canonical_from_oracle(d, procs, 0)
     for step in (0, 1):
         _one_step(d, procs, st, nid, step)
+
+
+@pytest.mark.parametrize("block,grid,sort_every", [(1024, 0, 7), (256, 2048, 3), (512, 5, 0)])
+def test_cost_balanced_push_ranges_deposit_every_electron_once(block, grid, sort_every):
+    """The electron push cuts the store where the previous launch's measured cost
+    reaches equal fractions: after every step the electron charge histogram is
+    exactly the deposit of the electron state (a range gap leaves electrons out,
+    an overlap deposits them twice), also when reordering shrinks the store between
+    launches and when most of a large grid gets empty ranges."""
+    from paper_0705_0497_amd.binding import Discharge
+    d = I.config(2)
+    g = Discharge(d, I.make_processes(), block=block, grid=grid, sort_every=sort_every)
+    g.load_uniform()
+    c0 = g.counters()
+    for k in range(24):
+        g.step(1)
+        st, _ = g.get_particles(0)
+        np.testing.assert_array_equal(g.hist()[0], po.deposit_canonical(d.ng, st["cell"], st["off"]),
+                                      err_msg=f"step {k}")
+    assert g.counters()[0] > c0[0]
+    g.close()
