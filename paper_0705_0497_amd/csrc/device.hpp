@@ -170,6 +170,7 @@ constexpr int CBLK = 1024;         // compaction blocks per species in a batch (
 struct BatchDev {
   int64_t base[MAXBATCH];          // step of each member when the running cycle began
   int32_t rows[NSP][MAXBATCH];     // partial-histogram rows written by the last batched push
+  PushBal bal;                     // electron push: tile ranges (in tiles) and durations per block
 };
 
 // launch shapes of a batch (host side)
@@ -179,7 +180,8 @@ struct BatchLaunch {
   int nmem;
   int block;                       // push block size
   int push_grid[NSP];              // persistent push grid per species
-  size_t push_lds[NSP];            // largest member LDS per species
+  size_t push_lds[NSP];            // largest member LDS per species (electrons: with the cut table)
+  size_t bal_lds;                  // electrons: LDS offset of the balanced cut table, 0 = equal ranges
   int nn_max;                      // largest ng + 1
   size_t diag_lds;
   int cgrid, pgrid, dgrid;         // compaction / pairing / diagnostics blocks per member

@@ -1846,15 +1846,54 @@ __device__ __forceinline__ long long block_of_tile(long long t, long long Tt, lo
   return ((t + 1) * G + Tt - 1) / Tt - 1;
 }
 
+// Cut points cut[0..G] of Tt tiles over G blocks for a batched electron push,
+// worked out by one wave: every block gets one tile, and the other Tt - G are
+// spread where the previous launch (other parity) measured the cumulative cost
+// of its blocks to reach equal fractions (its tile ranges mapped onto this
+// launch's tile count).  Without a map of G blocks the ranges are equal.
+__device__ void balanced_cuts(const PushBal *B, int par, long long G, long long Tt, long long *cut) {
+  const int lane = threadIdx.x & 63, prv = par ^ 1;
+  if (B->grid[prv] != (int)G || B->begin[prv][G] <= 0) {
+    for (long long j = lane; j <= G; j += 64) cut[j] = j * Tt / G;
+    return;
+  }
+  const int per = (int)((G + 63) / 64), k0 = (int)min(G, (long long)lane * per), k1 = (int)min(G, (long long)k0 + per);
+  double own = 0.0;
+  for (int k = k0; k < k1; ++k) own += (double)B->dur[prv][k];
+  const double incl = wave_incl_scan(own);
+  const double total = __shfl(incl, 63, 64);
+  double acc = __shfl_up(incl, 1, 64);          // integer tick sums: exact in FP64
+  if (lane == 0) acc = 0.0;
+  const double told = (double)B->begin[prv][G], extra = (double)(Tt - G);
+  for (int k = k0; k < k1; ++k) {
+    const double d = (double)B->dur[prv][k], nxt = acc + d;
+    // targets total j / G in [acc, nxt), each found by exactly one block k
+    long long j = max(1ll, (long long)(acc / total * (double)G));
+    while (j > 1 && total * (double)(j - 1) / (double)G >= acc) --j;
+    while (j < G && total * (double)j / (double)G < acc) ++j;
+    for (; j < G; ++j) {
+      const double T = total * (double)j / (double)G;
+      if (!(T < nxt)) break;
+      const double lo = (double)B->begin[prv][k], hi = (double)B->begin[prv][k + 1];
+      const double x = fmin(1.0, fmax(0.0, (lo + (T - acc) / d * (hi - lo)) / told));
+      cut[j] = j + (long long)(x * extra);
+    }
+    acc = nxt;
+  }
+  if (lane == 0) { cut[0] = 0; cut[G] = Tt; }
+}
+
 // Persistent push over all members in the mask.  The members' stores are cut
 // into tiles of one pass (GROUP * BS slots), numbered member after member; block
-// b takes the contiguous tile range b of min(grid, tiles) equal ranges, so its
-// work touches each member in at most one run.  The run's histogram goes to row
-// (b - first block of the member) of the member's partials; block 0 records the
-// number of rows per member for k_reduce_b.
+// b takes the contiguous tile range [cut[b], cut[b + 1]) (equal ranges of the
+// min(grid, tiles) blocks, or for electrons with bal_lds the ranges balanced by
+// the previous launch's cost, each at least one tile), so its work touches each
+// member in at most one run.  The run's histogram goes to row (b - first block of
+// the member) of the member's partials; block 0 records the number of rows per
+// member for k_reduce_b.
 template <int BS, int S_>
 __global__ __launch_bounds__(BS, PICMCC_PUSH_WAVES) void k_push_b(const Sim *__restrict__ sims, BatchDev *bd,
-                                                                  int nmem, uint64_t mask, int rel) {
+                                                                  int nmem, uint64_t mask, int rel, size_t bal_lds) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ PushLds pl;
   __shared__ long long tstart[MAXBATCH + 1];
@@ -1872,24 +1911,51 @@ __global__ __launch_bounds__(BS, PICMCC_PUSH_WAVES) void k_push_b(const Sim *__r
     if (m == 0) tstart[0] = 0;
   }
   __syncthreads();
+  const long long ts = (long long)__builtin_amdgcn_s_memrealtime();
   const long long Tt = tstart[nmem];
   const long long G = min((long long)gridDim.x, Tt);
+  const bool bal = S_ == 0 && bal_lds > 0 && G > 0;
+  const int par = rel & 1;
+  long long *cut = reinterpret_cast<long long *>(smem + bal_lds);   // [G + 1], past the push's LDS
+  if (bal) {
+    if (threadIdx.x < 64) balanced_cuts(&bd->bal, par, G, Tt, cut);
+    __syncthreads();
+  }
+  // block whose range holds tile t
+  auto block_of = [&](long long t) -> long long {
+    if (!bal) return block_of_tile(t, Tt, G);
+    long long lo = 0, hi = G - 1;
+    while (lo < hi) {
+      const long long mid = (lo + hi + 1) >> 1;
+      if (cut[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+  };
   if (blockIdx.x == 0 && threadIdx.x < nmem) {
     const int m = threadIdx.x;
     int rows = 0;
-    if (tstart[m + 1] > tstart[m])
-      rows = (int)(block_of_tile(tstart[m + 1] - 1, Tt, G) - block_of_tile(tstart[m], Tt, G) + 1);
+    if (tstart[m + 1] > tstart[m]) rows = (int)(block_of(tstart[m + 1] - 1) - block_of(tstart[m]) + 1);
     bd->rows[S_][m] = rows;
   }
   if ((long long)blockIdx.x >= G) return;
-  const long long t0 = (long long)blockIdx.x * Tt / G, t1 = ((long long)blockIdx.x + 1) * Tt / G;
+  const long long t0 = bal ? cut[blockIdx.x] : (long long)blockIdx.x * Tt / G;
+  const long long t1 = bal ? cut[blockIdx.x + 1] : ((long long)blockIdx.x + 1) * Tt / G;
   for (int m = 0; m < nmem; ++m) {
     const long long a = max(t0, tstart[m]), b = min(t1, tstart[m + 1]);
     if (a >= b) continue;
     const Sim &S = sims[m];
-    const long long row = (long long)blockIdx.x - block_of_tile(tstart[m], Tt, G);
+    const long long row = (long long)blockIdx.x - block_of(tstart[m]);
     const int64_t begin = (a - tstart[m]) * TILE, end = min((long long)nslot[m], (b - tstart[m]) * TILE);
     push_run<BS, S_>(S, bd->base[m] + rel, begin, end, S.part + (size_t)row * (S.ng + 1), smem, pl);
+  }
+  if (S_ == 0 && bal_lds > 0 && threadIdx.x == 0) {   // this launch's cost map for the next one
+    const long long te = (long long)__builtin_amdgcn_s_memrealtime();
+    bd->bal.begin[par][blockIdx.x] = t0;
+    bd->bal.dur[par][blockIdx.x] = max(1ll, te - ts);
+    if ((long long)blockIdx.x == G - 1) {
+      bd->bal.begin[par][G] = Tt;
+      bd->bal.grid[par] = (int32_t)G;
+    }
   }
 }
 
@@ -2161,9 +2227,9 @@ hipError_t launch_field_b(const BatchLaunch &B, int rel, hipStream_t st) {
 
 #define PUSHB_CASE(BS_)                                                                                       \
   case BS_:                                                                                                   \
-    if (s == 0) hipLaunchKernelGGL((k_push_b<BS_, 0>), dim3(g), dim3(BS_), lds, st, B.sims, B.bd, B.nmem, mask, rel); \
-    else if (s == 1) hipLaunchKernelGGL((k_push_b<BS_, 1>), dim3(g), dim3(BS_), lds, st, B.sims, B.bd, B.nmem, mask, rel); \
-    else hipLaunchKernelGGL((k_push_b<BS_, 2>), dim3(g), dim3(BS_), lds, st, B.sims, B.bd, B.nmem, mask, rel); \
+    if (s == 0) hipLaunchKernelGGL((k_push_b<BS_, 0>), dim3(g), dim3(BS_), lds, st, B.sims, B.bd, B.nmem, mask, rel, B.bal_lds); \
+    else if (s == 1) hipLaunchKernelGGL((k_push_b<BS_, 1>), dim3(g), dim3(BS_), lds, st, B.sims, B.bd, B.nmem, mask, rel, (size_t)0); \
+    else hipLaunchKernelGGL((k_push_b<BS_, 2>), dim3(g), dim3(BS_), lds, st, B.sims, B.bd, B.nmem, mask, rel, (size_t)0); \
     break;
 
 hipError_t launch_push_b(const BatchLaunch &B, int s, uint64_t mask, int rel, hipStream_t st) {

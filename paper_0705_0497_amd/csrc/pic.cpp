@@ -1084,6 +1084,18 @@ int batch_shapes(pic_batch *b) {
     const int g = b->cfg.grid ? b->cfg.grid : std::max(1, per_cu) * b->ncu;
     B.push_grid[s] = std::min(g, max_push_grid());
     B.push_lds[s] = lds;
+    if (s == 0) {
+      // the balanced electron ranges need a cut table past the push's LDS; only
+      // where it costs no occupancy
+      B.bal_lds = 0;
+      const size_t off = (lds + 15) & ~(size_t)15, tot = off + 8 * (size_t)(B.push_grid[0] + 1);
+      int per_cu_bal = 0;
+      if (tot <= b->lds_max) BHIP(b, batch_push_occupancy(B.block, 0, tot, &per_cu_bal));
+      if (tot <= b->lds_max && per_cu_bal >= std::max(1, per_cu)) {
+        B.push_lds[0] = tot;
+        B.bal_lds = off;
+      }
+    }
   }
   B.cgrid = 64;
   B.pgrid = 16;
