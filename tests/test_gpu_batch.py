@@ -94,7 +94,10 @@ def test_batch_direct_launches_and_launch_shapes():
     ref = _alone(ds, procs, stream, 2 * SPC)
     for kw in ({"block": 1024, "sort_every": 0, "use_graph": False},
                {"block": 512, "sort_every": 20, "use_graph": False, "grid": 3},
-               {"block": 256, "sort_every": 40, "use_graph": True, "grid": 1}):
+               {"block": 256, "sort_every": 40, "use_graph": True, "grid": 1},
+               # more blocks than tiles: the balanced electron cuts give every block one tile,
+               # and compaction every 10 steps changes the tile count between launches
+               {"block": 256, "sort_every": 10, "use_graph": True, "grid": 2048}):
         print("batch shapes", kw, flush=True)
         mem = _loaded(ds, procs, stream)
         b = Batch(mem, **kw)
