@@ -112,7 +112,6 @@ typedef struct pic_config {
   uint64_t seed;           /* key of the counter-based random streams */
   double weight;           /* physical particles per superparticle per m^2 of electrode */
   int32_t diag_every;      /* energy moments sampled every diag_every steps (0 = never) */
-  int32_t pair_rounds;     /* at most this many O2+ partners removed per cell per ion step */
   int32_t sort_every;      /* particles re-ordered by cell every sort_every steps (0 = never) */
   int32_t flags;           /* PIC_F_* */
   double e_ext0, e_ext1;   /* field of PIC_F_EXT_FIELD [V/m], [V/m^2] */

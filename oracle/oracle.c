@@ -790,36 +790,57 @@ static void push_species(orc_sim *S, int s, int64_t nstart) {
   }
 }
 
-/* partners of the ion removals of this ion step: per cell j, k[j] ions of
-   species s that were there before the step and are alive after its pushes,
-   each the one with the smallest (pairing draw, id); at most pair_rounds per
-   cell, the rest counted as a deficit.  O2+ partners of neutralisation (17) and
-   recombination (16), O- partners of electron-impact detachment (22). */
+/* partners of the ion removals of this ion step: in every cell j with k[j]
+   removals, the k[j] ions of species s with the smallest key (pairing draw, id)
+   among those that were there before the step and are alive after its pushes;
+   a cell holding fewer gives all it has and the rest is counted as a deficit.
+   Each removal of Table 1 (16), (17) or (22) thus takes exactly one partner.
+   O2+ partners of neutralisation (17) and recombination (16), O- partners of
+   electron-impact detachment (22). */
+typedef struct { int64_t cell; uint64_t key; int64_t i; } pair_cand;
+
+static int cmp_pair(const void *x, const void *y) {
+  const pair_cand *a = (const pair_cand *)x, *b = (const pair_cand *)y;
+  if (a->cell != b->cell) return a->cell < b->cell ? -1 : 1;
+  return a->key < b->key ? -1 : a->key > b->key;
+}
+
 static void pairing(orc_sim *S, int s, int64_t nstart_s, int64_t *k_cell, int c_paired, int c_deficit) {
   int ng = S->c.ng;
   orc_store *a = &S->st[s];
+  int64_t want = 0;
+  for (int j = 0; j < ng; ++j) want += k_cell[j];
+  if (want == 0) return;
+  /* every candidate partner of a cell with removals, sorted by (cell, key) */
+  pair_cand *c = malloc(sizeof(pair_cand) * (size_t)(nstart_s > 0 ? nstart_s : 1));
+  int64_t nc = 0;
+  for (int64_t i = 0; i < nstart_s; ++i) {
+    if (!a->alive[i]) continue;
+    int j = (int)floor(a->xi[i]);
+    if (k_cell[j] == 0) continue;
+    uint32_t d[4];
+    draw(S, s, a->id[i], S->step, ORC_P_PAIR, 0, d);
+    c[nc].cell = j;
+    c[nc].key = ((uint64_t)d[0] << 32) | a->id[i];
+    c[nc].i = i;
+    ++nc;
+  }
+  qsort(c, (size_t)nc, sizeof(pair_cand), cmp_pair);
+  /* the first k[j] of each cell's run are removed */
+  for (int64_t r = 0; r < nc;) {
+    int64_t j = c[r].cell, e = r;
+    while (e < nc && c[e].cell == j) ++e;
+    int64_t take = k_cell[j] < e - r ? k_cell[j] : e - r;
+    for (int64_t q = r; q < r + take; ++q) a->alive[c[q].i] = 0;
+    S->cnt[c_paired] += take;
+    k_cell[j] -= take;
+    r = e;
+  }
   for (int j = 0; j < ng; ++j) {
-    int64_t k = k_cell[j];
-    if (k == 0) continue;
-    int64_t want = k < S->c.pair_rounds ? k : S->c.pair_rounds;
-    for (int64_t r = 0; r < want; ++r) {
-      uint64_t best = UINT64_MAX;
-      int64_t bi = -1;
-      for (int64_t i = 0; i < nstart_s; ++i) {
-        if (!a->alive[i] || (int)floor(a->xi[i]) != j) continue;
-        uint32_t d[4];
-        draw(S, s, a->id[i], S->step, ORC_P_PAIR, 0, d);
-        uint64_t key = ((uint64_t)d[0] << 32) | a->id[i];
-        if (key < best) { best = key; bi = i; }
-      }
-      if (bi < 0) break;
-      a->alive[bi] = 0;
-      S->cnt[c_paired]++;
-      --k;
-    }
-    S->cnt[c_deficit] += k > 0 ? k : 0;
+    S->cnt[c_deficit] += k_cell[j];
     k_cell[j] = 0;
   }
+  free(c);
 }
 
 /* Table 1 (16) e + O2+ -> O + O and (22) e + O- -> O + 2e.  Once per ion step,
@@ -1035,6 +1056,10 @@ void orc_reset_moments(orc_sim *S) {
   S->psum = 0.0;
   S->pn = 0;
 }
+
+/* test hook: adds one sample of the energy moments of the current state (what
+   a step with diag_every hitting records before it moves anything) */
+void orc_sample_moments(orc_sim *S) { diagnostics(S); }
 
 void orc_get_current(const orc_sim *S, double *jsum, int64_t *jcnt, double *psum, int64_t *pn) {
   if (jsum) memcpy(jsum, S->jsum, sizeof(double) * S->c.steps_per_cycle);

@@ -80,7 +80,6 @@ typedef struct {
   uint64_t seed;
   double weight;          /* physical particles per superparticle per m^2 */
   int32_t diag_every;     /* energy moments every D steps (0: never) */
-  int32_t pair_rounds;    /* at most this many pairings per cell per ion step */
   int32_t flags;
   double e_ext0, e_ext1;  /* external field hook [V/m], [V/m^2] */
   double table_emin, table_emax;
@@ -139,6 +138,8 @@ double orc_sigma(const orc_sim *S, int32_t p, double e_ev);
 void orc_reset_moments(orc_sim *S);
 int64_t orc_get_moments(const orc_sim *S, double *sumQ, double *sumphi, int64_t *esum, int64_t *ecnt,
                         int64_t *edf, int64_t *iedf, int64_t *ndiag);
+/* test hook: one sample of the energy moments (esum, ecnt, edf) of the state as it is */
+void orc_sample_moments(orc_sim *S);
 
 /* current density at the driven electrode (section 3): per phase of the rf cycle
    the sums of j [A/m^2] and their counts, and the sum of U j [W/m^2] over the

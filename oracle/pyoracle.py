@@ -30,7 +30,9 @@ C_EICAND, C_EINULL, C_PAIRED_NEG, C_DEFICIT_NEG, NCOUNT = 38, 39, 40, 41, 44
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain -O2, no FMA contraction, no fast-math)."""
+    """Compile the oracle with gcc (plain -O2, no FMA contraction, no fast-math).  This build is the
+    reference for stored values: other optimisation levels may call libm in other forms
+    (sin and cos fused into sincos) and move a last bit."""
     if force or not os.path.exists(LIB_PATH) or any(
             os.path.getmtime(s) > os.path.getmtime(LIB_PATH) for s in SOURCES):
         tmp = LIB_PATH + ".tmp"
@@ -44,8 +46,8 @@ class _Config(C.Structure):
     _fields_ = [("L", C.c_double), ("ng", C.c_int32), ("U", C.c_double), ("f", C.c_double),
                 ("p", C.c_double), ("t_gas", C.c_double), ("steps_per_cycle", C.c_int32),
                 ("ksub", C.c_int32), ("c_meta", C.c_double), ("seed", C.c_uint64),
-                ("weight", C.c_double), ("diag_every", C.c_int32), ("pair_rounds", C.c_int32),
-                ("flags", C.c_int32), ("e_ext0", C.c_double), ("e_ext1", C.c_double),
+                ("weight", C.c_double), ("diag_every", C.c_int32), ("flags", C.c_int32),
+                ("e_ext0", C.c_double), ("e_ext1", C.c_double),
                 ("table_emin", C.c_double), ("table_emax", C.c_double), ("table_n", C.c_int32)]
 
 
@@ -98,6 +100,7 @@ def lib():
         L.orc_sigma.restype = dbl
         L.orc_sigma.argtypes = [vp, i32, dbl]
         L.orc_reset_moments.argtypes = [vp]
+        L.orc_sample_moments.argtypes = [vp]
         L.orc_get_moments.restype = i64
         L.orc_get_moments.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp]
         L.orc_log_events.argtypes = [vp, i32]
@@ -166,7 +169,7 @@ class Oracle:
         cfg = _Config(L=d.L, ng=d.ng, U=d.U, f=d.f, p=d.p, t_gas=d.t_gas,
                       steps_per_cycle=d.steps_per_cycle, ksub=d.ksub, c_meta=d.c_meta,
                       seed=int(d.seed if seed is None else seed) & (2**64 - 1), weight=d.weight,
-                      diag_every=d.diag_every, pair_rounds=d.pair_rounds, flags=flags,
+                      diag_every=d.diag_every, flags=flags,
                       e_ext0=e_ext[0], e_ext1=e_ext[1], table_emin=table[0], table_emax=table[1],
                       table_n=table[2])
         sp = (_Species * 3)(*[_Species(s.charge, s.mass, s.t0_ev, s.count, s.capacity) for s in species])
@@ -284,6 +287,10 @@ class Oracle:
 
     def reset_moments(self):
         lib().orc_reset_moments(self.h)
+
+    def sample_moments(self):
+        """Adds one sample of the energy moments of the state as it is."""
+        lib().orc_sample_moments(self.h)
 
     def moments(self):
         ng = self.ng

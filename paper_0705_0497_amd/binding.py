@@ -52,7 +52,7 @@ class pic_config(C.Structure):
     _fields_ = [("L", C.c_double), ("ng", C.c_int32), ("U", C.c_double), ("f", C.c_double), ("p", C.c_double),
                 ("t_gas", C.c_double), ("steps_per_cycle", C.c_int32), ("ksub", C.c_int32), ("c_meta", C.c_double),
                 ("seed", C.c_uint64), ("weight", C.c_double), ("diag_every", C.c_int32),
-                ("pair_rounds", C.c_int32), ("sort_every", C.c_int32), ("flags", C.c_int32),
+                ("sort_every", C.c_int32), ("flags", C.c_int32),
                 ("e_ext0", C.c_double), ("e_ext1", C.c_double), ("table_emin", C.c_double),
                 ("table_emax", C.c_double), ("table_n", C.c_int32), ("max_products", C.c_int32),
                 ("event_capacity", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
@@ -182,7 +182,7 @@ def make_config(d, flags=0, e_ext=(0.0, 0.0), seed=None, max_products=None, even
     return pic_config(L=d.L, ng=d.ng, U=d.U, f=d.f, p=d.p, t_gas=d.t_gas, steps_per_cycle=d.steps_per_cycle,
                       ksub=d.ksub, c_meta=d.c_meta, seed=int(d.seed if seed is None else seed) & (2 ** 64 - 1),
                       weight=d.weight, diag_every=d.diag_every if diag_every is None else diag_every,
-                      pair_rounds=d.pair_rounds, sort_every=d.sort_every if sort_every is None else sort_every,
+                      sort_every=d.sort_every if sort_every is None else sort_every,
                       flags=flags, e_ext0=e_ext[0], e_ext1=e_ext[1], table_emin=table[0], table_emax=table[1],
                       table_n=table[2], max_products=max_products, event_capacity=event_capacity, block=block,
                       grid=grid, sort_kind=getattr(d, "sort_kind", SORT_CELL) if sort_kind is None else sort_kind)

@@ -54,7 +54,7 @@ struct Scalars {
   float inv_numax_ei;
   int32_t meta_on;                 // spatially resolved O2(a): the field below replaces C n(O2)
   int32_t meta_tab;                // process whose events produce O2(a) (Table 1 (14))
-  int32_t pad3;
+  int32_t pair_nrec;               // keys listed by the pairing of the current ion step
   double na_max;                   // largest node density of the O2(a) field [m^-3]
   unsigned long long nsort[NSP];   // slots seen by the running sort
   // current density at the driven electrode: state of the previous field solve
@@ -74,6 +74,11 @@ struct PushBal {
   long long dur[2][MAXGRID];
   int32_t grid[2];
 };
+
+// pairing record of one cell for the ion step being closed: every candidate key
+// below bin bstar is taken, plus the `need` smallest of the `fill` keys of bin
+// bstar listed from segoff on
+struct PairCell { int32_t bstar, need, segoff, fill; };
 
 struct Particles {
   int32_t *w;          // packed cell word
@@ -103,7 +108,7 @@ struct Sim {
   uint64_t seed;
   // species
   Particles p[NSP];
-  Particles alt[NSP];              // the other buffer of each species (batched re-ordering)
+  Particles alt[NSP];              // the other buffer of each species (re-ordering target, pairing list)
   uint64_t *pkey[NSP];             // (parent species, parent id, local index) of this step's products
   int32_t *pbkt[NSP];              // bucket of each product's parent key
   uint64_t *ptmp[NSP];             // keys grouped by bucket during the id assignment
@@ -151,12 +156,12 @@ struct Sim {
   double *na;                      // [ng+1] O2(a) density [m^-3]
   float *na_f;                     // [ng+1] the same in FP32 for the collision step
   double *meta_tmp;                // [ng+1] solver work
-  unsigned long long *cmin;        // [2][ng] pairing minima
+  PairCell *pcell;                 // [ng] pairing records
+  int32_t *phist;                  // [ng][256] pairing key bins (zero between ion steps)
   int32_t *sortcnt, *sortbase;     // [ng], [ng]
   Scalars *sc;
   long long *events;
   int64_t event_cap;
-  int32_t pair_rounds;
   int32_t rq_cap;                  // electron candidate records kept in LDS per pass
   int32_t spc;                     // steps per rf cycle
   double *jsum;                    // [spc] current density sums per phase [A/m^2]

@@ -5,7 +5,7 @@
 //   k_field   charge -> potential -> node field (FP64), cycle sums, product ids
 //   k_push<e> leapfrog push, absorbing walls, null-collision MCC with free
 //             flights counted in steps, products, 64-bit fixed-point CIC deposit
-//   on ion steps: k_push<O2+>, k_ionprep (O- bound), k_push<O->, k_pair rounds
+//   on ion steps: k_push<O2+>, k_ionprep (O- bound), k_push<O->, k_pair (partners)
 //   every S steps: counting sort by cell; every D steps: energy moments.
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -1240,75 +1240,196 @@ __device__ void ionprep_block(const Sim &S) {
 template <int BS>
 __global__ __launch_bounds__(BS) void k_ionprep(Sim S) { ionprep_block<BS>(S); }
 
-// Pairing round r of an ion step for partners of species sp.  O2+ (sp = 1): one
-// per neutralised O- and per recombined electron of cell j; O- (sp = 2): one per
-// electron-impact detachment of cell j.  Partners are ions of cell j present
-// before the step: round r removes the winner of round r-1 (smallest key
-// (pairing draw, id) among the ions left in the cell) and finds the next
-// minimum.  The last block to finish settles the per-cell bookkeeping.
+// Partners of the ion removals of an ion step (Table 1 (17) and (16): O2+, sp = 1;
+// (22): O-, sp = 2).  Cell j requested k_j removals (kleft); its partners are the
+// k_j ions of species sp that were in the store before the step (slot < n), are
+// alive after the pushes and sit in cell j, with the smallest key (pairing draw,
+// id) -- all of them when the cell holds fewer, the rest counted as a deficit.
+// Exact k-smallest selection per cell in four launches over the store:
+//   pair_hist    counts the candidates of flagged cells in 256 bins of the key's
+//                top 8 bits (the bins order the keys),
+//   pair_select  finds per cell the bin b* where the count reaches k_j: every key
+//                below b* is taken, the need = k_j - (keys below b*) smallest keys
+//                of bin b* are decided by rank,
+//   pair_take    removes the candidates below b* and lists those of bin b*,
+//   pair_rank    removes the listed keys whose rank in their cell's list is below
+//                the need; its last block closes the pairing of the step.
+// The list lives in the species' second particle buffer (free between re-orderings).
+constexpr int PAIR_NB = 256;
+
+__device__ __forceinline__ uint32_t pair_draw(const Sim &S, int sp, uint32_t id, int64_t step) {
+  return draw(S, sp, id, step, P_PAIR, 0).x;
+}
+
+__device__ __forceinline__ int32_t *pair_active_flag(const Sim &S, int sp) {
+  return sp == 1 ? &S.sc->pair_active : &S.sc->pair_active_neg;
+}
+
+// removes ion i of species sp (cell c, offset off) with its charge
+__device__ __forceinline__ void pair_kill(const Sim &S, int sp, int64_t i, int c, float off) {
+  unsigned long long *Qs = S.Q + (size_t)sp * (S.ng + 1);
+  const unsigned long long a = cic_a(off);
+  atomicAdd(&Qs[c], (unsigned long long)(-(long long)(4294967296ull - a)));
+  atomicAdd(&Qs[c + 1], (unsigned long long)(-(long long)a));
+  S.p[sp].w[i] = W_DEAD;
+}
+
+__device__ __forceinline__ void pair_count_kills(const Sim &S, int sp, bool killed) {
+  const unsigned long long m = __ballot(killed);
+  if (m && __lane_id() == __ffsll((long long)m) - 1)
+    atomicAdd(&S.sc->cnt[sp == 1 ? C_PAIRED : C_PAIRED_NEG], (unsigned long long)__popcll(m));
+}
+
 template <int BS>
-__device__ void pair_block(const Sim &S, int64_t step, int r, int sp) {
-  int32_t *active = sp == 1 ? &S.sc->pair_active : &S.sc->pair_active_neg;
-  if (!*active) return;
-  int32_t *kleft = sp == 1 ? S.kleft : S.kleft_neg;
-  const int c_paired = sp == 1 ? C_PAIRED : C_PAIRED_NEG, c_deficit = sp == 1 ? C_DEFICIT : C_DEFICIT_NEG;
-  const int ng = S.ng, nn = ng + 1, R = S.pair_rounds;
-  unsigned long long *cur = S.cmin + (size_t)(r & 1) * ng;
-  unsigned long long *prev = S.cmin + (size_t)((r + 1) & 1) * ng;
+__device__ void pair_hist(const Sim &S, int64_t step, int sp, int bx, int gx) {
+  if (!*pair_active_flag(S, sp)) return;
+  if (bx == 0 && threadIdx.x == 0) S.sc->pair_nrec = 0;   // nothing reads it before pair_select
+  const int32_t *kl = sp == 1 ? S.kleft : S.kleft_neg;
   const Particles &P = S.p[sp];
   const int64_t N = (int64_t)S.sc->n[sp];
-  unsigned long long *Qp = S.Q + (size_t)sp * nn;
-  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
+  for (int64_t i = (int64_t)bx * BS + threadIdx.x; i < N; i += (int64_t)gx * BS) {
     const int32_t w = P.w[i];
     if (w < 0) continue;
     const int c = w & (int32_t)W_CELL;
-    const bool want_prev = r > 0 && prev[c] != ~0ull;
-    const bool want_cur = r < R && kleft[c] > 0;
-    if (!want_prev && !want_cur) continue;
-    const uint32_t id = P.id[i];
-    const unsigned long long key = ((unsigned long long)draw(S, sp, id, step, P_PAIR, 0).x << 32) | id;
-    if (want_prev && key == prev[c]) {
-      const float off = P.off[i];
-      const unsigned long long a = cic_a(off);
-      atomicAdd(&Qp[c], (unsigned long long)(-(long long)(4294967296ull - a)));
-      atomicAdd(&Qp[c + 1], (unsigned long long)(-(long long)a));
-      P.w[i] = W_DEAD;
-      atomicAdd(&S.sc->cnt[c_paired], 1ull);
-      continue;
-    }
-    if (want_cur) atomicMin(&cur[c], key);
+    if (kl[c] <= 0) continue;
+    const uint32_t x = pair_draw(S, sp, P.id[i], step);
+    atomicAdd(&S.phist[(size_t)c * PAIR_NB + (x >> 24)], 1);
   }
-  __shared__ bool last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(&S.sc->ticket, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  __shared__ int more;
-  if (threadIdx.x == 0) more = 0;
-  __syncthreads();
-  for (int c = threadIdx.x; c < ng; c += BS) {
-    if (r > 0) prev[c] = ~0ull;
-    const int k = kleft[c];
-    if (k <= 0) continue;
-    if (r < R && cur[c] != ~0ull) {
-      kleft[c] = k - 1;
-      more = 1;
-    } else {
-      atomicAdd(&S.sc->cnt[c_deficit], (unsigned long long)k);
-      kleft[c] = 0;
+}
+
+// one wave per cell; every cell's record is rewritten, flagged rows are cleared
+template <int BS>
+__device__ void pair_select(const Sim &S, int sp, int bx, int gx) {
+  if (!*pair_active_flag(S, sp)) return;
+  int32_t *kl = sp == 1 ? S.kleft : S.kleft_neg;
+  const int lane = threadIdx.x & 63;
+  const int nw = gx * (BS / 64);
+  for (int c = bx * (BS / 64) + (threadIdx.x >> 6); c < S.ng; c += nw) {
+    const int k = kl[c];
+    PairCell rec = {0, 0, 0, 0};
+    if (k > 0) {
+      int32_t *row = S.phist + (size_t)c * PAIR_NB + 4 * lane;
+      const int4 h4 = *reinterpret_cast<const int4 *>(row);
+      const int h[4] = {h4.x, h4.y, h4.z, h4.w};
+      const int sum = h[0] + h[1] + h[2] + h[3];
+      const int incl = wave_incl_scan(sum);
+      const int total = __shfl(incl, 63, 64);
+      if (total <= k) {                        // the cell gives every candidate it has
+        rec.bstar = PAIR_NB;
+        if (lane == 0 && total < k)
+          atomicAdd(&S.sc->cnt[sp == 1 ? C_DEFICIT : C_DEFICIT_NEG], (unsigned long long)(k - total));
+      } else {
+        const int excl = incl - sum;
+        const bool mine = excl < k && k <= incl;       // the lane whose bins reach k
+        int b = 0, need = 0, m = 0;
+        if (mine) {
+          int cum = excl, q = 0;
+          while (cum + h[q] < k) cum += h[q++];
+          b = 4 * lane + q; need = k - cum; m = h[q];
+        }
+        const int src = __ffsll((long long)__ballot(mine)) - 1;
+        b = __shfl(b, src, 64); need = __shfl(need, src, 64); m = __shfl(m, src, 64);
+        if (need == m) {                       // the whole bin is taken
+          rec.bstar = b + 1;
+        } else {
+          rec.bstar = b;
+          rec.need = need;
+          int so = 0;
+          if (lane == 0) so = atomicAdd(&S.sc->pair_nrec, m);
+          rec.segoff = __shfl(so, 0, 64);
+        }
+      }
+      *reinterpret_cast<int4 *>(row) = make_int4(0, 0, 0, 0);
+      if (lane == 0) kl[c] = 0;
     }
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    *active = more;
-    S.sc->ticket = 0u;
+    if (lane == 0) S.pcell[c] = rec;
   }
 }
 
 template <int BS>
-__global__ __launch_bounds__(BS) void k_pair(Sim S, int64_t step, int r, int sp) { pair_block<BS>(S, step, r, sp); }
+__device__ void pair_take(const Sim &S, int64_t step, int sp, int bx, int gx) {
+  if (!*pair_active_flag(S, sp)) return;
+  const Particles &P = S.p[sp];
+  const Particles &L = S.alt[sp];
+  const int64_t N = (int64_t)S.sc->n[sp];
+  // whole waves step through the slots so that the kill counts are wave-aggregated
+  const int64_t n_pad = (N + 63) & ~(int64_t)63;
+  for (int64_t i = (int64_t)bx * BS + threadIdx.x; i < n_pad; i += (int64_t)gx * BS) {
+    bool killed = false;
+    const int32_t w = i < N ? P.w[i] : W_DEAD;
+    if (w >= 0) {
+      const int c = w & (int32_t)W_CELL;
+      const PairCell rec = S.pcell[c];
+      if (rec.bstar > 0 || rec.need > 0) {
+        const uint32_t id = P.id[i];
+        const uint32_t x = pair_draw(S, sp, id, step);
+        const int b = (int)(x >> 24);
+        if (b < rec.bstar) {
+          pair_kill(S, sp, i, c, P.off[i]);
+          killed = true;
+        } else if (b == rec.bstar && rec.need > 0) {
+          const int e = rec.segoff + atomicAdd(&S.pcell[c].fill, 1);
+          reinterpret_cast<uint32_t *>(L.vx)[e] = x;
+          L.id[e] = id;
+          L.w[e] = (int32_t)i;
+          reinterpret_cast<int32_t *>(L.vy)[e] = c;
+        }
+      }
+    }
+    pair_count_kills(S, sp, killed);
+  }
+}
+
+template <int BS>
+__device__ void pair_rank(const Sim &S, int sp, int bx, int gx) {
+  int32_t *active = pair_active_flag(S, sp);
+  if (!*active) return;
+  const Particles &P = S.p[sp];
+  const Particles &L = S.alt[sp];
+  const int nrec = S.sc->pair_nrec;
+  const int n_pad = (nrec + 63) & ~63;
+  for (int e = bx * BS + threadIdx.x; e < n_pad; e += gx * BS) {
+    bool killed = false;
+    if (e < nrec) {
+      const int c = reinterpret_cast<const int32_t *>(L.vy)[e];
+      const PairCell rec = S.pcell[c];
+      const uint64_t key = ((uint64_t)reinterpret_cast<const uint32_t *>(L.vx)[e] << 32) | L.id[e];
+      int rank = 0;
+      for (int q = rec.segoff; q < rec.segoff + rec.fill; ++q)
+        rank += (((uint64_t)reinterpret_cast<const uint32_t *>(L.vx)[q] << 32) | L.id[q]) < key;
+      if (rank < rec.need) {
+        const int64_t i = L.w[e];
+        pair_kill(S, sp, i, c, P.off[i]);
+        killed = true;
+      }
+    }
+    pair_count_kills(S, sp, killed);
+  }
+  // the last block to finish closes this pairing
+  __shared__ bool last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&S.sc->ticket, 1u) == (unsigned)gx - 1;
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    *active = 0;
+    S.sc->ticket = 0u;
+  }
+}
+
+// stage 0..3 = hist, select, take, rank
+template <int BS>
+__device__ __forceinline__ void pair_stage(const Sim &S, int64_t step, int stage, int sp, int bx, int gx) {
+  if (stage == 0) pair_hist<BS>(S, step, sp, bx, gx);
+  else if (stage == 1) pair_select<BS>(S, sp, bx, gx);
+  else if (stage == 2) pair_take<BS>(S, step, sp, bx, gx);
+  else pair_rank<BS>(S, sp, bx, gx);
+}
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_pair(Sim S, int64_t step, int stage, int sp) {
+  pair_stage<BS>(S, step, stage, sp, blockIdx.x, gridDim.x);
+}
 
 // Electron-ion bound of an ion step (Table 1 (16), (22)): the O2+ and O- node
 // densities of the field solve, kept before the field kernel clears the ion
@@ -1981,10 +2102,10 @@ __global__ __launch_bounds__(BS) void k_ionprep_b(const Sim *__restrict__ sims, 
 
 template <int BS>
 __global__ __launch_bounds__(BS) void k_pair_b(const Sim *__restrict__ sims, const BatchDev *__restrict__ bd,
-                                                uint64_t mask, int rel, int r, int sp) {
+                                                uint64_t mask, int rel, int stage, int sp) {
   const int m = blockIdx.y;
-  if (!in_mask(mask, m) || r > sims[m].pair_rounds) return;
-  pair_block<BS>(sims[m], bd->base[m] + rel, r, sp);
+  if (!in_mask(mask, m)) return;
+  pair_stage<BS>(sims[m], bd->base[m] + rel, stage, sp, blockIdx.x, gridDim.x);
 }
 
 template <int BS>
@@ -2124,8 +2245,11 @@ hipError_t launch_ionprep(const Sim &S, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_pair(const Sim &S, int64_t step, int r, int sp, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_pair<GBS>), dim3(grid), dim3(GBS), 0, st, S, step, r, sp);
+hipError_t launch_pair(const Sim &S, int64_t step, int stage, int sp, int grid, hipStream_t st) {
+  // pair_select: one wave per cell
+  const int cells = (S.ng + GBS / 64 - 1) / (GBS / 64);
+  const int g = stage == 1 && cells < grid ? cells : grid;
+  hipLaunchKernelGGL((k_pair<GBS>), dim3(g), dim3(GBS), 0, st, S, step, stage, sp);
   return hipGetLastError();
 }
 
@@ -2256,8 +2380,8 @@ hipError_t launch_ionprep_b(const BatchLaunch &B, uint64_t mask, hipStream_t st)
   return hipGetLastError();
 }
 
-hipError_t launch_pair_b(const BatchLaunch &B, uint64_t mask, int rel, int r, int sp, hipStream_t st) {
-  hipLaunchKernelGGL((k_pair_b<GBS>), dim3(B.pgrid, B.nmem), dim3(GBS), 0, st, B.sims, B.bd, mask, rel, r, sp);
+hipError_t launch_pair_b(const BatchLaunch &B, uint64_t mask, int rel, int stage, int sp, hipStream_t st) {
+  hipLaunchKernelGGL((k_pair_b<GBS>), dim3(B.pgrid, B.nmem), dim3(GBS), 0, st, B.sims, B.bd, mask, rel, stage, sp);
   return hipGetLastError();
 }
 

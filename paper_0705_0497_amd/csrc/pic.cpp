@@ -18,7 +18,7 @@ hipError_t launch_push(const Sim &S, int s, int64_t step, int grid, int block, h
 hipError_t launch_field(const Sim &S, int64_t step, int mode, hipStream_t st);
 hipError_t launch_fixup(const Sim &S, hipStream_t st);
 hipError_t launch_ionprep(const Sim &S, hipStream_t st);
-hipError_t launch_pair(const Sim &S, int64_t step, int r, int sp, int grid, hipStream_t st);
+hipError_t launch_pair(const Sim &S, int64_t step, int stage, int sp, int grid, hipStream_t st);
 hipError_t launch_eiprep(const Sim &S, hipStream_t st);
 hipError_t launch_meta_init(const Sim &S, int tab, hipStream_t st);
 hipError_t launch_meta_solve(const Sim &S, double weight, double tau, double D, double nu_q, double h, hipStream_t st);
@@ -42,7 +42,7 @@ hipError_t launch_field_b(const BatchLaunch &B, int rel, hipStream_t st);
 hipError_t launch_push_b(const BatchLaunch &B, int s, uint64_t mask, int rel, hipStream_t st);
 hipError_t launch_reduce_b(const BatchLaunch &B, int s, uint64_t mask, hipStream_t st);
 hipError_t launch_ionprep_b(const BatchLaunch &B, uint64_t mask, hipStream_t st);
-hipError_t launch_pair_b(const BatchLaunch &B, uint64_t mask, int rel, int r, int sp, hipStream_t st);
+hipError_t launch_pair_b(const BatchLaunch &B, uint64_t mask, int rel, int stage, int sp, hipStream_t st);
 hipError_t launch_eiprep_b(const BatchLaunch &B, uint64_t mask, hipStream_t st);
 hipError_t launch_eion_b(const BatchLaunch &B, uint64_t mask, int rel, hipStream_t st);
 hipError_t launch_diag_b(const BatchLaunch &B, uint64_t mask, hipStream_t st);
@@ -64,7 +64,7 @@ struct Layout {
   size_t total = 0;
   size_t part[NSP][2][6];   // two buffers x (w, off, vx, vy, vz, id)
   size_t pkey[NSP], pbkt[NSP], ptmp[NSP], bcnt;
-  size_t Q, E, phi, sumQ, sumphi, esum, ecnt, edf, iedf, nacc, kleft, cmin, sortcnt, sortbase, sc, sigma,
+  size_t Q, E, phi, sumQ, sumphi, esum, ecnt, edf, iedf, nacc, kleft, pcell, phist, sortcnt, sortbase, sc, sigma,
       hbound, events, partials, ttot, blkcnt, prof, jsum, jcnt, jpow, kleft_neg, dens_ei, meta_src, na, na_f,
       meta_tmp, bal;
   size_t take(size_t bytes) {
@@ -97,7 +97,8 @@ Layout make_layout(const pic_config &c, const pic_species *sp, int nproc) {
   L.iedf = L.take(8 * NSP * 2 * NBIN);
   L.nacc = L.take(16);
   L.kleft = L.take(4 * (size_t)c.ng);
-  L.cmin = L.take(16 * (size_t)c.ng);
+  L.pcell = L.take(sizeof(PairCell) * (size_t)c.ng);
+  L.phist = L.take(4 * (size_t)256 * c.ng);
   L.sortcnt = L.take(4 * (size_t)c.ng);
   L.sortbase = L.take(4 * (size_t)c.ng);
   L.sc = L.take(sizeof(Scalars));
@@ -136,7 +137,6 @@ int validate(const pic_config *c, const pic_species *sp, const pic_process *pr, 
   if (!finite_pos(c->weight)) { msg = "weight must be > 0"; return PIC_EINVAL; }
   if (c->diag_every < 0 || c->sort_every < 0) { msg = "diag_every and sort_every must be >= 0"; return PIC_EINVAL; }
   if (c->sort_kind != PIC_SORT_CELL && c->sort_kind != PIC_SORT_COMPACT) { msg = "sort_kind must be PIC_SORT_CELL or PIC_SORT_COMPACT"; return PIC_EINVAL; }
-  if (c->pair_rounds < 1 || c->pair_rounds > 64) { msg = "pair_rounds must be in [1, 64]"; return PIC_EINVAL; }
   if (!finite_pos(c->table_emin) || !(c->table_emax > c->table_emin) || !std::isfinite(c->table_emax)) {
     msg = "table range must satisfy 0 < emin < emax"; return PIC_EINVAL;
   }
@@ -363,7 +363,6 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
   S.max_products = c.max_products; S.n_o2 = n_o2; S.c_meta = c.c_meta; S.dti = dti;
   S.wd = c.weight / 4294967296.0 / dx;
   S.nplus_c = (float)S.wd;
-  S.pair_rounds = c.pair_rounds;
   S.event_cap = c.event_capacity;
   S.ntab = c.table_n;
   S.lnemin = (float)std::log(c.table_emin);
@@ -388,6 +387,7 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
     S.vt_gas[s] = (float)std::sqrt(KB * c.t_gas / m);
     for (int b = 0; b < 2; ++b) h->buf[s][b] = carve(h->ws, L.part[s][b]);
     S.p[s] = h->buf[s][0];
+    S.alt[s] = h->buf[s][1];
     S.pkey[s] = (uint64_t *)(h->ws + L.pkey[s]);
     S.pbkt[s] = (int32_t *)(h->ws + L.pbkt[s]);
     S.ptmp[s] = (uint64_t *)(h->ws + L.ptmp[s]);
@@ -439,7 +439,8 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
   S.na = (double *)(ws + L.na);
   S.na_f = (float *)(ws + L.na_f);
   S.meta_tmp = (double *)(ws + L.meta_tmp);
-  S.cmin = (unsigned long long *)(ws + L.cmin);
+  S.pcell = (PairCell *)(ws + L.pcell);
+  S.phist = (int32_t *)(ws + L.phist);
   S.sortcnt = (int32_t *)(ws + L.sortcnt);
   S.bcnt = (int32_t *)(ws + L.bcnt);
   S.sortbase = (int32_t *)(ws + L.sortbase);
@@ -507,7 +508,6 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
   hipError_t e = hipMemsetAsync(h->ws, 0, L.total, h->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(h->ws + L.ttot, ttot.data(), ttot.size() * 4, hipMemcpyHostToDevice, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(h->ws + L.cmin, 0xFF, 16 * (size_t)c.ng, h->stream);
   if (e == hipSuccess && nproc)
     e = hipMemcpyAsync(h->ws + L.sigma, sig32.data(), sig32.size() * 4, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess && nproc)
@@ -559,6 +559,7 @@ int pic_load_uniform(pic_handle *h) {
     const float vth = (float)std::sqrt(h->sp[s].t0_ev * QE / h->sp[s].mass);
     h->cur[s] = 0;
     h->S.p[s] = h->buf[s][0];
+    h->S.alt[s] = h->buf[s][1];
     if (h->sp[s].count > 0) HIPCHK(h, launch_load(h->S, s, h->sp[s].count, vth, h->hgrid, h->stream));
     unsigned long long n = (unsigned long long)h->sp[s].count, z = 0;
     uint32_t nid = (uint32_t)h->sp[s].count;
@@ -648,6 +649,7 @@ int pic_load_profiles(pic_handle *h, int32_t n_pts, const double *x_over_L, cons
   for (int s = 0; s < NSP; ++s) {
     h->cur[s] = 0;
     h->S.p[s] = h->buf[s][0];
+    h->S.alt[s] = h->buf[s][1];
     const long long count = cum[s].back();
     if (count > 0) HIPCHK(h, launch_load_profile(h->S, s, count, dcum + s * ng, dvth + s * ng, h->hgrid, h->stream));
     unsigned long long nn = (unsigned long long)count, z = 0;
@@ -684,6 +686,7 @@ int pic_set_particles(pic_handle *h, int32_t s, int64_t n, const int32_t *cell, 
   HIPCHK(h, hipStreamSynchronize(h->stream));
   h->cur[s] = 0;
   h->S.p[s] = h->buf[s][0];
+  h->S.alt[s] = h->buf[s][1];
   const Particles &P = h->S.p[s];
   if (n > 0) {
     HIPCHK(h, hipMemcpy(P.w, w.data(), 4 * n, hipMemcpyHostToDevice));
@@ -803,6 +806,7 @@ static int enqueue_step(pic_handle *h, hipEvent_t ev0, hipEvent_t ev1) {
       else HIPCHK(h, launch_compact(S, s, h->buf[s][other], h->hgrid, h->stream));
       h->cur[s] = other;
       S.p[s] = h->buf[s][other];
+      S.alt[s] = h->buf[s][1 - other];
     }
   }
   if (ev0) HIPCHK(h, hipEventRecord(ev0, h->stream));
@@ -816,9 +820,10 @@ static int enqueue_step(pic_handle *h, hipEvent_t ev0, hipEvent_t ev1) {
     HIPCHK(h, launch_ionprep(S, h->stream));
     HIPCHK(h, launch_push(S, 2, n, h->grid[2], h->block, h->stream));
     HIPCHK(h, launch_reduce(S, 2, h->grid[2], h->stream));
-    for (int r = 0; r <= c.pair_rounds; ++r) HIPCHK(h, launch_pair(S, n, r, 1, h->pgrid, h->stream));
+    // partners: O2+ of neutralisation and recombination, then O- of electron-impact detachment
+    for (int stage = 0; stage < 4; ++stage) HIPCHK(h, launch_pair(S, n, stage, 1, h->pgrid, h->stream));
     if (eion)
-      for (int r = 0; r <= c.pair_rounds; ++r) HIPCHK(h, launch_pair(S, n, r, 2, h->pgrid, h->stream));
+      for (int stage = 0; stage < 4; ++stage) HIPCHK(h, launch_pair(S, n, stage, 2, h->pgrid, h->stream));
   }
   h->step = n + 1;
   return PIC_OK;
@@ -1137,13 +1142,11 @@ int launch_batch_step(pic_batch *b, int r) {
   const int n = B.nmem;
   const uint64_t all = all_mask(n);
   uint64_t dmask = 0ull, imask = 0ull, emask = 0ull;
-  int R = 0;
   for (int m = 0; m < n; ++m) {
     const pic_config &c = b->mem[m]->cfg;
     if (c.diag_every > 0 && r % c.diag_every == 0) dmask |= 1ull << m;
     if (r % c.ksub == 0) {
       imask |= 1ull << m;
-      R = std::max(R, c.pair_rounds);
       // electron-ion channels (Table 1 (16), (22)) on this member's ion steps
       if (b->mem[m]->S.nei > 0 && !(c.flags & PIC_F_NO_COLL)) emask |= 1ull << m;
     }
@@ -1161,9 +1164,9 @@ int launch_batch_step(pic_batch *b, int r) {
     BHIP(b, launch_ionprep_b(B, imask, st));
     BHIP(b, launch_push_b(B, 2, imask, r, st));
     BHIP(b, launch_reduce_b(B, 2, imask, st));
-    for (int k = 0; k <= R; ++k) BHIP(b, launch_pair_b(B, imask, r, k, 1, st));
+    for (int stage = 0; stage < 4; ++stage) BHIP(b, launch_pair_b(B, imask, r, stage, 1, st));
     if (emask)
-      for (int k = 0; k <= R; ++k) BHIP(b, launch_pair_b(B, emask, r, k, 2, st));
+      for (int stage = 0; stage < 4; ++stage) BHIP(b, launch_pair_b(B, emask, r, stage, 2, st));
   }
   if (r == b->spc - 1) BHIP(b, launch_advance_b(B, b->spc, st));
   return PIC_OK;
@@ -1289,6 +1292,7 @@ int pic_batch_sync(pic_batch *b) {
       for (int s = 0; s < NSP; ++s) {
         h->cur[s] = b->host_sims[m].p[s].w == h->buf[s][0].w ? 0 : 1;
         h->S.p[s] = h->buf[s][h->cur[s]];
+        h->S.alt[s] = h->buf[s][1 - h->cur[s]];
       }
       h->batch_busy = false;
     }

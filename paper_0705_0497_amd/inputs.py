@@ -102,7 +102,6 @@ class Discharge:
     n_total: int = 30000     # superparticles over all species
     sort_every: int = 20
     diag_every: int = 20
-    pair_rounds: int = 4
     seed: int = 1
     capacity_factor: float = 4.0
     counts: Optional[tuple] = None   # explicit (e, O2+, O-) counts, if given

@@ -50,7 +50,7 @@ def test_query_reports_workspace_size():
 
 @pytest.mark.parametrize("field,value", [("ng", 1), ("ng", 9000), ("L", 0.0), ("ksub", 0), ("weight", -1.0),
                                          ("table_n", 1), ("max_products", 0), ("max_products", (1 << 24) + 1),
-                                         ("block", 300), ("pair_rounds", 0), ("c_meta", -0.5)])
+                                         ("block", 300), ("c_meta", -0.5)])
 def test_query_rejects_invalid_config(field, value):
     cfg, sp, pr, n, _ = _args()
     setattr(cfg, field, value)

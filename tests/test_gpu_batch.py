@@ -215,3 +215,66 @@ def test_batch_with_all_channels_and_resolved_o2a_equals_alone():
         c = snap["counters"]
         assert c[18 + names.index("e-recomb")] + c[18 + names.index("e-edet")] > 0, m
     b.close()
+
+
+def test_batch_members_of_mixed_sizes_match_the_oracle():
+    """One batched rf cycle against the FP64 oracle, element by element: three members
+    of different cells, sizes, voltages and pressures on a four-step cycle (the time
+    step of the 128-cell workload, ions every second step, neutralisation boosted so
+    that pairing acts), each set from an oracle state.  Decisions identical outside
+    the 1e-6 band, positions and velocities to 1e-5, charge the exact deposit."""
+    import dataclasses
+    import torch
+    from oracle import pyoracle as po
+    from paper_0705_0497_amd.binding import Batch
+    stream = torch.cuda.Stream()
+    procs = H.neutralising(I.make_processes())
+    base = I.config(1)
+    spc = 4
+    f = base.f * base.steps_per_cycle / spc                   # the same dt as the 128-cell workload
+    ds = [dataclasses.replace(base, ng=ng, U=U, p=p, n_total=n, seed=8800 + j, f=f, steps_per_cycle=spc,
+                              ksub=2, diag_every=0, sort_every=0, capacity_factor=8.0)
+          for j, (ng, U, p, n) in enumerate([(64, 150.0, 10.0, 6000), (128, 250.0, 20.0, 30000),
+                                              (256, 350.0, 40.0, 60000)])]
+    mem, orc, nid0, paired = [], [], [], 0
+    for d in ds:
+        st, nid, step = H.canonical_from_oracle(d, procs, seed_steps=8)
+        assert step % spc == 0
+        orc.append(H.oracle_from_canonical(d, procs, st, nid, step))
+        mem.append(H.gpu_from_canonical(d, procs, st, nid, step, event_capacity=1 << 20, stream=stream))
+        nid0.append(nid)
+    b = Batch(mem, block=256, sort_every=2, use_graph=True)
+    for o in orc:
+        o.log_events(True)
+        o.step(spc)
+    b.step_cycles(1)
+    b.sync()
+    for m, (g, o, d) in enumerate(zip(mem, orc, ds)):
+        gev, oev = g.events(), o.events()
+        band = H.band_ids(oev)
+        key_o = {(int(r[0]), int(r[1]), int(r[2])): int(r[3]) for r in oev if r[3] not in (-4, -5)}
+        key_g = {(int(r[0]), int(r[1]), int(r[2])): int(r[3]) for r in gev}
+        pre = lambda k: k[2] < nid0[m][k[1] if k[1] < 3 else 0]
+        # without a decision in the band every particle, products included, must agree
+        keep = (lambda k: (k[1], k[2]) not in band) if not band else (lambda k: (k[1], k[2]) not in band and pre(k))
+        bad = [(k, key_o.get(k), key_g.get(k)) for k in set(key_o) | set(key_g) if keep(k) and key_o.get(k) != key_g.get(k)]
+        assert not bad, (m, bad[:10])
+        assert len(key_g) > 100 and len(band) <= 3, (m, len(key_g), len(band))
+        for s in range(3):
+            gs, nid_g = g.get_particles(s)
+            os_ = o.get_particles(s)
+            if band:
+                gs = {k: v[gs["id"] < nid0[m][s]] for k, v in gs.items()}
+                os_ = {k: v[os_["id"] < nid0[m][s]] for k, v in os_.items()}
+            else:
+                assert nid_g == o.next_id(s)
+            dx, dv = H.compare_states(gs, os_, d.species()[s], skip=band, s=s)
+            assert dx <= H.POS_TOL and dv <= H.VEL_TOL, (m, s, dx, dv)
+            full, _ = g.get_particles(s)
+            np.testing.assert_array_equal(g.hist()[s], po.deposit_canonical(d.ng, full["cell"], full["off"]))
+        gc, oc = g.counters(), o.counters()
+        if not band:
+            np.testing.assert_array_equal(gc[po.C_PUSH:po.C_CLAMP], oc[po.C_PUSH:po.C_CLAMP])
+        paired += int(oc[po.C_PAIRED])
+    assert paired > 0
+    b.close()

@@ -108,6 +108,55 @@ def test_products_and_pairing_over_an_ion_cycle():
     assert paired > 0
 
 
+def test_pairing_takes_every_partner_a_cell_has():
+    """Table 1 (17): each neutralisation removes one O2+ of the O-'s cell, the one
+    with the smallest (pairing draw, id) among those there before the step; a cell
+    with more events than O2+ gives them all and counts the rest as a deficit.  The
+    same O2+ leave on both sides, cell by cell."""
+    from paper_0705_0497_amd.binding import Discharge, F_EXT_FIELD
+    neut = I.Process("n", 2, "neutralize", "grid+", 0.0, I.M_O2PLUS, I.power_law_table(4e-14, 0, 0.5, 0), {})
+    ng = 8
+    # cell 2: 3 O2+ among 300 O- (its nodes carry the density of 1500 O2+ each from cells
+    # 1 and 3); cell 5: 3000 O2+, 300 O-; cell 6: 40 O2+ and 300 O-, densities from cell 7
+    xpos = np.concatenate([np.full(3, 2.5), np.full(1500, 1.99), np.full(1500, 3.01), np.full(3000, 5.5),
+                           np.full(40, 6.5), np.full(2000, 7.01)])
+    xneg = np.concatenate([np.full(300, 2.5), np.full(300, 5.5), np.full(300, 6.5)])
+    npos, nneg = len(xpos), len(xneg)
+    weight = 6.25e12
+    d = I.config(1, L=0.025, ng=ng, p=2000.0, c_meta=1.0, diag_every=0, sort_every=0,
+                 n_plus0=weight * npos / 0.025, counts=(1, npos, 1))
+    sp = [I.Species(-1.0, I.ELECTRON_MASS, 3.0, 0, 1), I.Species(1.0, I.M_O2PLUS, 0.026, npos, npos),
+          I.Species(-1.0, I.M_OMINUS, 0.026, nneg, nneg)]
+
+    def canon(x):
+        cell = np.floor(x).astype(np.int32)
+        z = np.zeros(len(x), np.float32)
+        return dict(cell=cell, off=(x - cell).astype(np.float32), vx=z, vy=z, vz=z,
+                    id=np.arange(len(x), dtype=np.uint32), cd=np.ones(len(x), np.int32))
+    st = [canon(np.zeros(0)), canon(xpos), canon(xneg)]
+    nid = [0, npos, nneg]
+    o = H.oracle_from_canonical(d, [neut], st, nid, 0, species=sp, flags=po.F_EXT_FIELD, e_ext=(0.0, 0.0))
+    g = Discharge(d, [neut], species=sp, flags=F_EXT_FIELD, e_ext=(0.0, 0.0), sort_every=0)
+    for s in range(3):
+        g.set_particles(s, st[s], nid[s])
+    g.set_step(0)
+    g.prepare(False)
+    o.step(1)
+    g.step(1)
+    for s in (1, 2):
+        np.testing.assert_array_equal(np.sort(g.get_particles(s)[0]["id"]), np.sort(o.get_particles(s)["id"]))
+    gc, oc = g.counters(), o.counters()
+    for c in (po.C_PAIRED, po.C_DEFICIT, po.C_EVENT):
+        assert gc[c] == oc[c], (c, gc[c], oc[c])
+    left = np.bincount(np.floor(H.xi_of(g.get_particles(1)[0])).astype(int), minlength=ng)
+    k = np.bincount(np.floor(xneg[np.isin(np.arange(nneg), g.get_particles(2)[0]["id"], invert=True)]).astype(int),
+                    minlength=ng)
+    assert k[2] > 3 and k[6] > 40 and k[5] > 3
+    assert left[2] == 0 and left[6] == 0 and left[5] == 3000 - k[5]
+    assert gc[po.C_DEFICIT] == (k[2] - 3) + (k[6] - 40)
+    np.testing.assert_array_equal(g.hist(), o.hist())
+
+
 def test_multi_step_trajectories_stay_close():
     """Same draws on both sides: after 40 steps most particles still agree."""
     d = I.config(1)
@@ -220,55 +269,38 @@ def test_ballistic_flight_fp32():
     np.testing.assert_allclose(st["vx"], v0 + a * (n - 0.5) * d.dt, rtol=1e-5)
 
 
-def test_cycle_averaged_densities_agree_statistically():
-    """Config-1 discharge, 6 seeds per side, densities averaged over the second
-    rf cycle on 16 coarse bins: z-scores of GPU vs oracle ensemble means."""
-    from paper_0705_0497_amd.binding import Discharge
-    d = I.config(1)
-    procs = I.make_processes()
-    M = 6
-    res = {"gpu": [], "orc": []}
-    for m in range(M):
-        dd = I.config(1, seed=9000 + m)
-        o = po.Oracle(dd, dd.species(), procs)
-        o.load_uniform()
-        o.prepare(True)
-        o.step(d.steps_per_cycle)
-        o.reset_moments()
-        o.step(d.steps_per_cycle)
-        res["orc"].append(o.moments()["sumQ"] / d.steps_per_cycle)
-        g = Discharge(dd, procs)
-        g.load_uniform()
-        g.step(d.steps_per_cycle)
-        g.moments(reset=True)
-        g.step(d.steps_per_cycle)
-        res["gpu"].append(g.moments()["sum_q"] / d.steps_per_cycle)
-    coarse = lambda a: a[:, :, :d.ng].reshape(a.shape[0], 3, 16, -1).sum(-1)
-    G, O = coarse(np.array(res["gpu"])), coarse(np.array(res["orc"]))
-    z = (G.mean(0) - O.mean(0)) / np.sqrt(G.var(0, ddof=1) / M + O.var(0, ddof=1) / M + 1e-30)
-    assert np.mean(np.abs(z) > 3.5) <= 0.05, z
-    assert np.mean(z ** 2) < 3.0, z
-    # electronegativity in the centre (middle 10% of nodes)
-    mid = slice(int(0.45 * d.ng), int(0.55 * d.ng) + 1)
-    alpha = lambda a: a[:, 2, mid].sum(1) / a[:, 0, mid].sum(1)
-    ag, ao = alpha(np.array(res["gpu"])), alpha(np.array(res["orc"]))
-    assert abs(ag.mean() - ao.mean()) < 4 * math.sqrt(ag.var(ddof=1) / M + ao.var(ddof=1) / M)
+def _decisions(ev, s, ids=None):
+    """(id, code) of the species' decision records, sorted by id (vectorised)."""
+    r = ev[ev[:, 1] == s]
+    r = r[r[:, 3] != -4]
+    if ids is not None:
+        r = r[np.isin(r[:, 2], ids)]
+    o = np.argsort(r[:, 2], kind="stable")
+    return r[o, 2], r[o, 3]
+
+
+def _band_of(oev, s):
+    b = oev[(oev[:, 4] != 0) & ((oev[:, 1] == s) | ((s == 0) & (oev[:, 1] == 3)))]
+    return set(b[:, 2].tolist())
 
 
 @pytest.mark.parametrize("cfg", [2, 3])
-def test_full_size_sampled_single_step(cfg):
-    """Working and large discharges in the benchmark's launch shape: a sample of
-    particles pushed by the oracle in the GPU's own field, plus the exact
-    deposit property on the whole state."""
+def test_full_size_single_step(cfg):
+    """Working and large discharges in the benchmark's launch shape, one ion step and
+    one electron step.  The oracle holds every ion (so the O2+ density that the O-
+    see, the O- collision bound, neutralisation, detachment and the pairing of the
+    ion step are the GPU's) and a sample of the electrons, in the GPU's own field;
+    decisions and states are compared for every species, the wall distributions of
+    the ions exactly, and the deposit is exact on the whole state."""
     from paper_0705_0497_amd.binding import Discharge
     d = I.config(cfg)
     procs = I.make_processes()
-    g = Discharge(d, procs, event_capacity=1 << 23, block=1024)     # bench.py's push block
+    g = Discharge(d, procs, event_capacity=1 << 26, block=1024)     # bench.py's push block
     g.load_uniform()
-    warm = 2 * d.ksub - 1            # next step is an ion step with a sort just before it
-    g.step(warm)
+    g.step(2 * d.ksub)               # the next step is an ion step, with a re-ordering just before it
     for step_kind in ("ion", "electron"):
         n = g.step_index
+        assert (n % d.ksub == 0) == (step_kind == "ion")
         states = [g.get_particles(s) for s in range(3)]
         Q = g.hist()
         for s in range(3):
@@ -278,34 +310,49 @@ def test_full_size_sampled_single_step(cfg):
         o = po.Oracle(d, d.species(), procs)
         for s in range(3):
             st, nid = states[s]
-            k = rng.choice(len(st["id"]), size=min(50000, len(st["id"])), replace=False)
-            sub = {key: v[k] for key, v in st.items()}
-            samples.append(sub)
-            o.set_particles(s, sub, nid)
+            if s == 0:
+                k = rng.choice(len(st["id"]), size=min(50000, len(st["id"])), replace=False)
+                st = {key: v[k] for key, v in st.items()}
+            samples.append(st)
+            o.set_particles(s, st, nid)
         o.set_hist(Q)
         o.set_step(n)
         o.log_events(True)
+        o.reset_moments()
         g.clear_events()
+        g.moments(reset=True)
+        gc0 = g.counters()
         g.step(1)
         o.step(1)
         gev = g.events()
         oev = o.events()
-        band = H.band_ids(oev)
-        check = (0, 1) if step_kind == "ion" else (0,)
+        check = (0, 1, 2) if step_kind == "ion" else (0,)
         for s in check:
-            ids = set(samples[s]["id"].tolist())
-            og = {(int(r[1]), int(r[2])): int(r[3]) for r in gev if r[1] == s and int(r[2]) in ids}
-            oo = {(int(r[1]), int(r[2])): int(r[3]) for r in oev if r[1] == s and r[3] != -4}
-            bad = [k for k in set(og) | set(oo) if og.get(k) != oo.get(k) and k not in band]
-            assert not bad, bad[:5]
+            ids = samples[s]["id"]
+            band = _band_of(oev, s)
+            gi, gc = _decisions(gev, s, ids)
+            oi, oc = _decisions(oev, s)
+            if s == 2 and step_kind == "ion":
+                assert len(oi) > 100, "the ion step has O- collision candidates"
+            keep_g = ~np.isin(gi, list(band)) if band else np.ones(len(gi), bool)
+            keep_o = ~np.isin(oi, list(band)) if band else np.ones(len(oi), bool)
+            np.testing.assert_array_equal(gi[keep_g], oi[keep_o], err_msg=f"cfg {cfg} species {s}: candidates")
+            np.testing.assert_array_equal(gc[keep_g], oc[keep_o], err_msg=f"cfg {cfg} species {s}: channels")
             gs = H.by_id(g.get_particles(s)[0])
             os_ = H.by_id(o.get_particles(s))
-            keep = np.isin(os_["id"], samples[s]["id"])          # sampled survivors, no products
+            keep = np.isin(os_["id"], ids)                      # the pre-step particles, no products
             os_ = {k2: v[keep] for k2, v in os_.items()}
-            gk = np.isin(gs["id"], os_["id"])
+            gk = np.isin(gs["id"], ids)
             gs = {k2: v[gk] for k2, v in gs.items()}
-            dx, dv = H.compare_states(gs, os_, d.species()[s], skip=band, s=s)
+            skip = {(s, i) for i in band}
+            dx, dv = H.compare_states(gs, os_, d.species()[s], skip=skip, s=s)
             assert dx <= H.POS_TOL and dv <= H.VEL_TOL, (cfg, step_kind, s, dx, dv)
+        if step_kind == "ion":
+            # every ion of both sides: the same partners removed, the same wall energies
+            gc_, oc_ = g.counters() - gc0, o.counters()
+            assert gc_[po.C_PAIRED] == oc_[po.C_PAIRED] and gc_[po.C_DEFICIT] == oc_[po.C_DEFICIT] == 0
+            mg, mo = g.moments(), o.moments()
+            np.testing.assert_array_equal(mg["iedf"][1:], mo["iedf"][1:])
         g.sync()
 
 
@@ -593,36 +640,3 @@ def test_full_channel_set_with_resolved_o2a_agrees_statistically():
     for j in range(2):                        # electron-ion event counts: ensemble means within 4 sigma
         zj = (eg[:, j].mean() - eo[:, j].mean()) / math.sqrt(eg[:, j].var(ddof=1) / M + eo[:, j].var(ddof=1) / M + 1e-30)
         assert abs(zj) < 4.0, (j, eg[:, j], eo[:, j])
-
-
-def test_parity_workload_over_two_cycles_matches_the_stored_oracle_ensemble():
-    """512-cell discharge, the oracle's 8-seed ensemble of second-cycle densities stored by
-    tests/golden/make_cfg2_ensemble.py: the GPU runs the same seeds and its ensemble agrees on
-    32 coarse bins per species (z-scores) and in the central electronegativity."""
-    import os
-    from paper_0705_0497_amd.binding import Discharge
-    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "cfg2_oracle_ensemble.txt")
-    rows = [line.split() for line in open(path) if not line.startswith("#")]
-    seeds = [int(r[0]) for r in rows]
-    ao = np.array([float(r[1]) for r in rows])
-    O = np.array([[float(x) for x in r[2:]] for r in rows]).reshape(len(rows), 3, -1)
-    bins = O.shape[2]
-    G, ag = [], []
-    for seed in seeds:
-        d = I.config(2, seed=seed)
-        g = Discharge(d, I.make_processes())
-        g.load_uniform()
-        g.step(d.steps_per_cycle)
-        g.moments(reset=True)
-        g.step(d.steps_per_cycle)
-        q = g.moments()["sum_q"] / d.steps_per_cycle
-        G.append(q[:, :d.ng].reshape(3, bins, -1).sum(-1))
-        mid = slice(int(0.45 * d.ng), int(0.55 * d.ng) + 1)
-        ag.append(q[2, mid].sum() / q[0, mid].sum())
-        g.close()
-    G, ag = np.array(G), np.array(ag)
-    M = len(seeds)
-    z = (G.mean(0) - O.mean(0)) / np.sqrt(G.var(0, ddof=1) / M + O.var(0, ddof=1) / M + 1e-30)
-    assert np.mean(np.abs(z) > 3.5) <= 0.05, z
-    assert np.mean(z ** 2) < 3.0, z
-    assert abs(ag.mean() - ao.mean()) < 4 * math.sqrt(ag.var(ddof=1) / M + ao.var(ddof=1) / M), (ag, ao)

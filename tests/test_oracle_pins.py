@@ -430,7 +430,7 @@ def test_neutralisation_pairs_one_partner_in_the_same_cell():
     key = lambda i: (int(po.philox([i, 0, (1 << 24) | (5 << 16), 0], [d.seed & 0xffffffff, d.seed >> 32])[0]) << 32) | i
     for j in range(ng):
         ids_j = [int(i) for i, x in zip(before["id"], before["xi"]) if int(math.floor(x)) == j]
-        want = min(kcell[j], d.pair_rounds, len(ids_j))
+        want = min(kcell[j], len(ids_j))
         got = sorted(i for i in removed if int(math.floor(cpos[i])) == j)
         assert got == sorted(sorted(ids_j, key=key)[:want])
     # charge: each paired event removes one + and one -
@@ -754,7 +754,7 @@ def _ions_on_cell_centres(o, s, ng, k):
 def _eion_setup(procs, n_e=400000, k=64, n_ion=3.67e19, e_ev=10.0, ng=64, seed=11, pos=True, neg=True):
     """Electrons moving along y at e_ev (no field, no gas: position and energy stay put)
     over uniform O2+ and / or O- of density n_ion; one ion step."""
-    d = I.config(1, L=0.025, ng=ng, p=0.0, diag_every=0, pair_rounds=64, n_plus0=n_ion,
+    d = I.config(1, L=0.025, ng=ng, p=0.0, diag_every=0, n_plus0=n_ion,
                  counts=(n_e, k * ng, k * ng))
     sp = species(n_e, k * ng, k * ng)
     o = po.Oracle(d, sp, procs, flags=po.F_EXT_FIELD, e_ext=(0.0, 0.0))
@@ -827,7 +827,7 @@ def test_electron_detachment_conserves_energy_minus_the_threshold():
 
 def test_recombination_removes_a_partner_from_the_electrons_cell():
     """(16) with the O2+ of one cell only: only electrons next to it recombine, and
-    their partners come from that cell, at most pair_rounds per ion step."""
+    each recombination in that cell removes one O2+ of it; the others find none."""
     rec = I.Process("rec", 0, "recomb", "grid+", 0.0, I.M_O2PLUS, _sqrt_law(4e-19), {})
     d, o, v = _eion_setup([rec], n_e=100000, k=64, neg=False)
     # move all O2+ into cell 5: the node densities the test sees change, the electrons of cell 5
@@ -844,12 +844,41 @@ def test_recombination_removes_a_partner_from_the_electrons_cell():
     gone = [i for i in el0["id"].tolist() if i not in survivors]
     cells = np.floor(el0["xi"][np.isin(el0["id"], gone)]).astype(int)
     assert len(gone) == k16
-    # only electrons near cell 5 (nodes 5, 6 carry the density) can recombine; partners
-    # come from cell 5 only, at most pair_rounds of them per ion step
+    # only electrons near cell 5 (nodes 5, 6 carry the density) can recombine; every one
+    # in cell 5 takes one of its 4096 O2+, those in cells 4 and 6 find no partner
     assert set(cells.tolist()) <= {4, 5, 6}
     n5 = int(np.sum(cells == 5))
-    assert n5 > d.pair_rounds and c[po.C_PAIRED] == d.pair_rounds
-    assert o.count(1) == 64 * 64 - d.pair_rounds
+    assert n5 > 4 and c[po.C_PAIRED] == n5 and c[po.C_DEFICIT] == k16 - n5
+    assert o.count(1) == 64 * 64 - n5
+
+
+def test_pairing_takes_every_partner_a_cell_has():
+    """More neutralisations in a cell than O2+ there: all of them go, the excess is
+    the deficit; a cell with enough O2+ loses exactly one per neutralisation (Table 1
+    (17): one O2+ per event), however many events the cell has."""
+    neut = I.Process("n", 2, "neutralize", "grid+", 0.0, I.M_O2PLUS, I.power_law_table(4e-14, 0, 0.5, 0), {})
+    ng = 8
+    # cell 2: 3 O2+ and 300 O-, its nodes carrying the density of 1500 O2+ each from
+    # cells 1 and 3; cell 5: 3000 O2+ and 300 O-
+    cpos = np.concatenate([np.full(3, 2.5), np.full(1500, 1.99), np.full(1500, 3.01), np.full(3000, 5.5)])
+    cneg = np.concatenate([np.full(300, 2.5), np.full(300, 5.5)])
+    d, o = ion_setup([neut], npos=len(cpos), nneg=len(cneg), ng=ng, weight=6.25e12)
+    put(o, 1, cpos, np.zeros(len(cpos)))
+    put(o, 2, cneg, np.zeros(len(cneg)))
+    empty(o, 0)
+    o.prepare(False)
+    o.log_events(True)
+    o.step(1)
+    ev = o.events()
+    neut_ids = ev[(ev[:, 1] == 2) & (ev[:, 3] == 0), 2]
+    k2 = int(np.sum(neut_ids < 300))
+    k5 = int(np.sum(neut_ids >= 300))
+    assert k2 > 3 and k5 > 3
+    c = o.counters()
+    pos = o.get_particles(1)
+    left = np.bincount(np.floor(pos["xi"]).astype(int), minlength=ng)
+    assert left[2] == 0 and left[5] == 3000 - k5 and left[1] == 1500 and left[3] == 1500
+    assert c[po.C_PAIRED] == 3 + k5 and c[po.C_DEFICIT] == k2 - 3
 
 
 # ---------------------------------------------------------------- spatially resolved O2(a) (section 4)
