@@ -66,6 +66,22 @@ int mlp_get_params(mlp_handle *h, float *host_params);
    Asynchronous. */
 int mlp_forward(mlp_handle *h, int32_t batch, const float *x, float *y);
 
+/* Inference for callers that cannot allocate device memory or enqueue copies
+   (code under HIP graph capture, tight serving loops, harnesses that forbid
+   allocation): the same outputs as mlp_forward, bit for bit, with the hidden
+   activations in a static array of the library (MLP_STATIC_SCRATCH_BYTES per
+   device, held until the process ends) instead of the handle's workspace, and
+   the outputs written straight into y.  Allocates nothing and makes no copy.
+   1 <= batch <= MLP_STATIC_MAX_BATCH, else PIC_EINVAL.  x [batch][3] and
+   y [batch][6] are FP32 device arrays.  Asynchronous on the handle's stream.
+   Every call on one device shares that device's array: calls that overlap in
+   time on one device (other streams, other threads, other handles) race.
+   Nothing in the array needs clearing: each call writes what it reads. */
+#define MLP_STATIC_MAX_BATCH 4096
+#define MLP_STATIC_SCRATCH_BYTES 8413184   /* the input (256-aligned), then 8 B per hidden unit per sample:
+                                              a 4 B pre-activation and two 2 B activation buffers */
+int mlp_forward_static(mlp_handle *h, int32_t batch, const float *x, float *y);
+
 /* Training pass: forward with the activations kept, loss
    L = mean over the batch and the 6 outputs of (y - t)^2 for targets
    t [batch][6] (FP32, device), then the gradient of L with respect to every

@@ -38,8 +38,9 @@ EXPORTS = ("pic_version", "pic_query", "pic_create", "pic_destroy", "pic_load_un
            "pic_batch_set_config", "pic_batch_get_config", "pic_batch_autotune", "pic_batch_destroy",
            "pic_batch_last_error", "pic_ksub_select", "pic_metastable_config", "pic_metastable_update")
 MLP_EXPORTS = ("mlp_query", "mlp_create", "mlp_destroy", "mlp_set_params", "mlp_get_params", "mlp_forward",
-               "mlp_backward", "mlp_get_grads", "mlp_adam", "mlp_last_error")
+               "mlp_forward_static", "mlp_backward", "mlp_get_grads", "mlp_adam", "mlp_last_error")
 MLP_NPARAM = 199942
+MLP_STATIC_MAX_BATCH = 4096      # largest batch of mlp_forward_static
 
 
 class PicError(RuntimeError):
@@ -146,6 +147,7 @@ def lib():
         L.mlp_set_params.argtypes = [vp, vp]
         L.mlp_get_params.argtypes = [vp, vp]
         L.mlp_forward.argtypes = [vp, i32, vp, vp]
+        L.mlp_forward_static.argtypes = [vp, i32, vp, vp]
         L.mlp_backward.argtypes = [vp, i32, vp, vp, vp]
         L.mlp_get_grads.argtypes = [vp, vp]
         L.mlp_adam.argtypes = [vp, C.c_float, C.c_float, C.c_float, C.c_float]
@@ -600,6 +602,12 @@ def mlp_get_params(h):
 
 def mlp_forward(h, batch, x_ptr, y_ptr):
     _mcheck(lib().mlp_forward(h, int(batch), C.c_void_p(x_ptr), C.c_void_p(y_ptr)), h)
+
+
+def mlp_forward_static(h, batch, x_ptr, y_ptr):
+    """Inference with the activations in the library's static per-device array
+    (no allocation, no copy); batch <= MLP_STATIC_MAX_BATCH."""
+    _mcheck(lib().mlp_forward_static(h, int(batch), C.c_void_p(x_ptr), C.c_void_p(y_ptr)), h)
 
 
 def mlp_backward(h, batch, x_ptr, t_ptr, want_loss=True):

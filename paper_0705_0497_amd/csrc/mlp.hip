@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "../../include/mlp.h"
@@ -231,10 +232,42 @@ Layout make_layout(int64_t B) {
 
 std::string g_err;
 
+// Activations of mlp_forward_static: one file-scope array per device (each GPU
+// the library runs on holds its copy until the process ends).  Layout for up to
+// MLP_STATIC_MAX_BATCH samples: the bfloat16 input, one FP32 pre-activation
+// buffer and two bfloat16 activation buffers used in turn by the hidden layers.
+constexpr size_t ST_XB = 0;
+constexpr size_t ST_Z = ((size_t)MLP_STATIC_MAX_BATCH * MLP_NIN * 2 + 255) & ~(size_t)255;
+constexpr size_t ST_ACT0 = ST_Z + (size_t)MLP_STATIC_MAX_BATCH * MLP_NHID * 4;
+constexpr size_t ST_ACT1 = ST_ACT0 + (size_t)MLP_STATIC_MAX_BATCH * MLP_NHID * 2;
+constexpr size_t ST_BYTES = ST_ACT1 + (size_t)MLP_STATIC_MAX_BATCH * MLP_NHID * 2;
+static_assert(ST_BYTES == MLP_STATIC_SCRATCH_BYTES, "scratch size stated in mlp.h");
+
+static __device__ __align__(256) unsigned char scratch[ST_BYTES];
+
+// device address of `scratch` per device, looked up once with that device current
+constexpr int MAX_DEVICES = 64;
+unsigned char *g_scratch_dev[MAX_DEVICES] = {};
+std::mutex g_scratch_mu;
+
+hipError_t scratch_address(int dev, unsigned char **out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[dev] = (unsigned char *)p;
+  }
+  *out = g_scratch_dev[dev];
+  return hipSuccess;
+}
+
 }  // namespace
 
 struct mlp_handle {
   int32_t max_batch = 0;
+  unsigned char *scratch = nullptr;   // this device's activation array of mlp_forward_static
   Layout L;
   unsigned char *ws = nullptr;
   hipStream_t stream = nullptr;
@@ -266,36 +299,52 @@ hipError_t gemm(const GemmArgs &g, int split, hipStream_t st) {
 
 int grid_of(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 255) / 256, 4096)); }
 
-// forward pass over `batch` samples of x (FP32, device); outputs in the workspace
-int run_forward(mlp_handle *h, int32_t batch, const float *x) {
-  const Layout &L = h->L;
+// Forward pass over `batch` samples of x (FP32, device) into y.  xb: the
+// bfloat16 input; z[l], act[l]: pre-activation (FP32) and activation (bfloat16)
+// of hidden layer l (the buffers of different layers may coincide when only the
+// output is wanted and act[l] != act[l - 1]).
+struct FwdBufs { __bf16 *xb; float *z[NL - 1]; __bf16 *act[NL - 1]; };
+
+int forward_into(mlp_handle *h, int32_t batch, const float *x, const FwdBufs &b, float *y) {
   hipStream_t st = h->stream;
   const int64_t nx = (int64_t)batch * MLP_NIN;
-  hipLaunchKernelGGL(k_to_bf16, dim3(grid_of(nx)), dim3(256), 0, st, x, h->at<__bf16>(L.xb), nx);
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid_of(nx)), dim3(256), 0, st, x, b.xb, nx);
   MHIP(h, hipGetLastError());
   for (int l = 0; l < NL; ++l) {
     GemmArgs g{};
-    g.A = l == 0 ? h->at<__bf16>(L.xb) : h->at<__bf16>(L.act[l - 1]);
+    g.A = l == 0 ? b.xb : b.act[l - 1];
     g.sam = INS[l];
     g.sak = 1;
-    g.B = h->at<__bf16>(L.p16) + w_off(l);       // B(k, n) = W[n][k]
+    g.B = h->at<__bf16>(h->L.p16) + w_off(l);       // B(k, n) = W[n][k]
     g.sbk = 1;
     g.sbn = INS[l];
     g.M = batch;
     g.N = OUTS[l];
     g.K = INS[l];
     g.kchunk = INS[l];
-    g.bias = h->at<float>(L.p32) + b_off(l);
+    g.bias = h->at<float>(h->L.p32) + b_off(l);
     if (l + 1 < NL) {
-      g.C = h->at<float>(L.z[l]);
-      g.C16 = h->at<__bf16>(L.act[l]);
+      g.C = b.z[l];
+      g.C16 = b.act[l];
       MHIP(h, gemm<EPI_HIDDEN>(g, 1, st));
     } else {
-      g.C = h->at<float>(L.y);
+      g.C = y;
       MHIP(h, gemm<EPI_OUT>(g, 1, st));
     }
   }
   return PIC_OK;
+}
+
+// forward pass with every activation kept in the workspace (training)
+int run_forward(mlp_handle *h, int32_t batch, const float *x) {
+  const Layout &L = h->L;
+  FwdBufs b;
+  b.xb = h->at<__bf16>(L.xb);
+  for (int l = 0; l < NL - 1; ++l) {
+    b.z[l] = h->at<float>(L.z[l]);
+    b.act[l] = h->at<__bf16>(L.act[l]);
+  }
+  return forward_into(h, batch, x, b, h->at<float>(L.y));
 }
 
 int refresh_bf16(mlp_handle *h) {
@@ -328,8 +377,13 @@ int mlp_create(int32_t max_batch, void *workspace, uint64_t bytes, void *stream,
     return fail(nullptr, PIC_ENODEVICE, "no HIP device");
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(nullptr, PIC_ENODEVICE, std::string("device is ") + prop.gcnArchName + ", kernels are for gfx950");
+  unsigned char *scr = nullptr;
+  const hipError_t es = scratch_address(dev, &scr);
+  if (es != hipSuccess)
+    return fail(nullptr, PIC_EHIP, std::string("mlp_create: hipGetSymbolAddress(scratch): ") + hipGetErrorString(es));
   mlp_handle *h = new mlp_handle();
   h->max_batch = max_batch;
+  h->scratch = scr;
   h->L = make_layout(max_batch);
   h->ws = (unsigned char *)workspace;
   h->stream = (hipStream_t)stream;
@@ -371,6 +425,20 @@ int mlp_forward(mlp_handle *h, int32_t batch, const float *x, float *y) {
   if (rc != PIC_OK) return rc;
   MHIP(h, hipMemcpyAsync(y, h->at<float>(h->L.y), 4 * (size_t)batch * MLP_NOUT, hipMemcpyDeviceToDevice, h->stream));
   return PIC_OK;
+}
+
+int mlp_forward_static(mlp_handle *h, int32_t batch, const float *x, float *y) {
+  if (!h || !x || !y) return fail(h, PIC_EINVAL, "null handle, x or y");
+  if (batch < 1 || batch > MLP_STATIC_MAX_BATCH)
+    return fail(h, PIC_EINVAL, "mlp_forward_static: batch must be in [1, " + std::to_string(MLP_STATIC_MAX_BATCH) +
+                                   "] (the size of the library's static activation array)");
+  FwdBufs b;
+  b.xb = reinterpret_cast<__bf16 *>(h->scratch + ST_XB);
+  for (int l = 0; l < NL - 1; ++l) {
+    b.z[l] = reinterpret_cast<float *>(h->scratch + ST_Z);
+    b.act[l] = reinterpret_cast<__bf16 *>(h->scratch + ((l & 1) ? ST_ACT1 : ST_ACT0));
+  }
+  return forward_into(h, batch, x, b, y);
 }
 
 int mlp_backward(mlp_handle *h, int32_t batch, const float *x, const float *t, float *loss_host) {
