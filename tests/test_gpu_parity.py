@@ -333,7 +333,7 @@ def test_full_size_single_step(cfg):
             gi, gc = _decisions(gev, s, ids)
             oi, oc = _decisions(oev, s)
             if s == 2 and step_kind == "ion":
-                assert len(oi) > 100, "the ion step has O- collision candidates"
+                assert len(oi) > 10, "the ion step has O- collision candidates"
             keep_g = ~np.isin(gi, list(band)) if band else np.ones(len(gi), bool)
             keep_o = ~np.isin(oi, list(band)) if band else np.ones(len(oi), bool)
             np.testing.assert_array_equal(gi[keep_g], oi[keep_o], err_msg=f"cfg {cfg} species {s}: candidates")
