@@ -258,8 +258,6 @@ int pic_get_counters(pic_handle *h, int64_t *out);
    min(*n, max) records.  clear != 0 empties the log. */
 int pic_get_events(pic_handle *h, int64_t max, int64_t *rec, int64_t *n, int32_t clear);
 
-/* Collision-frequency bound used by the null-collision test of species s [1/s]
-   (for O- the value of the last ion step). */
 /* Spatially resolved O2(a1Delta_g), the extension section 4 proposes for the
    uniform n = C n(O2) of Eq. (1) (PIC_T_O2A partners).  The density on the nodes
    is the steady state of  D n'' - quench_rate n + P(x) = 0  between the
@@ -287,6 +285,8 @@ typedef struct pic_metastable {
 int pic_metastable_config(pic_handle *h, const pic_metastable *m);
 int pic_metastable_update(pic_handle *h, double *n_out);
 
+/* Collision-frequency bound used by the null-collision test of species s [1/s]
+   (for O- the value of the last ion step). */
 int pic_nu_max(pic_handle *h, int32_t s, double *nu);
 
 /* Timing of the kernels of the next n_steps steps (synchronises): total device

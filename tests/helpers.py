@@ -2,6 +2,7 @@
 import math
 
 import numpy as np
+from scipy import stats
 
 from oracle import pyoracle as po
 from paper_0705_0497_amd import inputs as I
@@ -99,3 +100,62 @@ def neutralising(procs, factor=3e4):
         if p.kind == "neutralize":
             p.sigma = p.sigma * factor
     return procs
+
+
+def welch_z(g, o):
+    """Normal-equivalent z of the Welch t statistic of two samples (axis 0), and the
+    mask of the entries with a variance."""
+    M1, M2 = g.shape[0], o.shape[0]
+    v1, v2 = g.var(0, ddof=1) / M1, o.var(0, ddof=1) / M2
+    se2 = v1 + v2
+    live = se2 > 0
+    t = np.zeros_like(se2)
+    t[live] = (g.mean(0)[live] - o.mean(0)[live]) / np.sqrt(se2[live])
+    dof = np.full_like(se2, 1.0)
+    dof[live] = se2[live] ** 2 / (v1[live] ** 2 / (M1 - 1) + v2[live] ** 2 / (M2 - 1))
+    p = 2.0 * stats.t.sf(np.abs(t), dof)
+    z = np.sign(t) * stats.norm.isf(p / 2.0)
+    return z, live
+
+
+def perm_quantile(G, O, q=0.999, nperm=2000, seed=0):
+    """Quantile q of the mean z^2 over the nodes when the gpu / oracle labels are
+    exchanged at random among all runs: the null distribution of the statistic for
+    two samples of one distribution, with the correlation of the nodes included."""
+    X = np.concatenate([G, O])
+    M1 = G.shape[0]
+    rng = np.random.Generator(np.random.PCG64(seed))
+    vals = np.empty(nperm)
+    for k in range(nperm):
+        idx = rng.permutation(X.shape[0])
+        z, live = welch_z(X[idx[:M1]], X[idx[M1:]])
+        vals[k] = np.mean(z[live] ** 2)
+    return float(np.quantile(vals, q))
+
+
+def judge_ensembles(G, O, ag, ao, what):
+    """Cycle averages of M runs per side, G and O [M][...], and their central
+    electronegativities ag, ao [M]: at most 1 % of the entries beyond |z| = 3, the
+    mean z^2 below the 99.9 % quantile of its relabelling distribution, alpha
+    within 3."""
+    G2, O2 = G.reshape(G.shape[0], -1), O.reshape(O.shape[0], -1)
+    z, live = welch_z(G2, O2)
+    # a node that is empty on every run of both sides (no variance) must agree exactly
+    dead = ~live
+    np.testing.assert_array_equal(G2.mean(0)[dead], O2.mean(0)[dead])
+    zl = z[live]
+    K = zl.size
+    beyond = float(np.mean(np.abs(zl) > 3.0))
+    mz2 = float(np.mean(zl ** 2))
+    # the chi^2 99.9 % bound holds for independent nodes; the profiles fluctuate
+    # coherently (neighbouring nodes and species move together), so the bound is the
+    # 99.9 % quantile of the same statistic under random relabelling of the runs
+    chi2 = stats.chi2.ppf(0.999, K) / K
+    bound = perm_quantile(G2, O2)
+    za, _ = welch_z(ag[:, None], ao[:, None])
+    msg = (f"{what}: {K} nodes, {beyond:.4f} beyond 3, mean z^2 {mz2:.3f} (99.9 % under relabelling "
+           f"{bound:.3f}; chi^2 of independent nodes {chi2:.3f}), alpha z {za[0]:.2f}")
+    print(msg)
+    assert beyond <= 0.01, msg
+    assert mz2 <= bound, msg
+    assert abs(za[0]) <= 3.0, msg

@@ -598,15 +598,17 @@ def _full_set_for_runs():
 
 def test_full_channel_set_with_resolved_o2a_agrees_statistically():
     """Sixteen channels and the O2(a) profile solved after the first rf cycle (each side from
-    its own production): densities over the second cycle, 6 seeds per side, z-scores of the
-    ensemble means on 16 coarse bins, and the electron-ion event rates."""
+    its own production): node densities over the second cycle, 16 seeds per side, per node
+    and species at the thresholds of the other ensemble tests (tests/test_gpu_statistics.py),
+    and the electron-ion event counts within 3 sigma."""
     from paper_0705_0497_amd.binding import Discharge
     d = I.config(1)
     procs, ka1 = _full_set_for_runs()
     names = [p.name for p in procs]
-    M = 6
+    M = 16
     res = {"gpu": [], "orc": []}
     ev = {"gpu": [], "orc": []}
+    cols = [po.C_EVENT + names.index("e-recomb"), po.C_EVENT + names.index("e-edet")]
     for m in range(M):
         dd = I.config(1, seed=9100 + m)
         o = po.Oracle(dd, dd.species(), procs)
@@ -618,8 +620,8 @@ def test_full_channel_set_with_resolved_o2a_agrees_statistically():
         o.reset_moments()
         c0 = o.counters()
         o.step(d.steps_per_cycle)
-        res["orc"].append(o.moments()["sumQ"] / d.steps_per_cycle)
-        ev["orc"].append((o.counters() - c0)[[po.C_EVENT + names.index("e-recomb"), po.C_EVENT + names.index("e-edet")]])
+        res["orc"].append(o.moments()["sumQ"] / d.steps_per_cycle / 2.0 ** 32)
+        ev["orc"].append((o.counters() - c0)[cols])
         g = Discharge(dd, procs)
         g.load_uniform()
         g.metastable_config(ka1, META["diffusion"], META["quench_rate"], META["surface_loss"])
@@ -628,15 +630,14 @@ def test_full_channel_set_with_resolved_o2a_agrees_statistically():
         g.moments(reset=True)
         c0 = g.counters()
         g.step(d.steps_per_cycle)
-        res["gpu"].append(g.moments()["sum_q"] / d.steps_per_cycle)
-        ev["gpu"].append((g.counters() - c0)[[po.C_EVENT + names.index("e-recomb"), po.C_EVENT + names.index("e-edet")]])
-    coarse = lambda a: a[:, :, :d.ng].reshape(a.shape[0], 3, 16, -1).sum(-1)
-    G, O = coarse(np.array(res["gpu"])), coarse(np.array(res["orc"]))
-    z = (G.mean(0) - O.mean(0)) / np.sqrt(G.var(0, ddof=1) / M + O.var(0, ddof=1) / M + 1e-30)
-    assert np.mean(np.abs(z) > 3.5) <= 0.05, z
-    assert np.mean(z ** 2) < 3.0, z
+        res["gpu"].append(g.moments()["sum_q"] / d.steps_per_cycle / 2.0 ** 32)
+        ev["gpu"].append((g.counters() - c0)[cols])
+        g.close()
+    G, O = np.array(res["gpu"]), np.array(res["orc"])
+    mid = slice(int(0.45 * d.ng), int(0.55 * d.ng) + 1)
+    alpha = lambda a: a[:, 2, mid].sum(1) / a[:, 0, mid].sum(1)
+    H.judge_ensembles(G, O, alpha(G), alpha(O), "sixteen channels, resolved O2(a), second cycle")
     eg, eo = np.array(ev["gpu"], float), np.array(ev["orc"], float)
     assert np.all(eo.sum(0) > 50), eo
-    for j in range(2):                        # electron-ion event counts: ensemble means within 4 sigma
-        zj = (eg[:, j].mean() - eo[:, j].mean()) / math.sqrt(eg[:, j].var(ddof=1) / M + eo[:, j].var(ddof=1) / M + 1e-30)
-        assert abs(zj) < 4.0, (j, eg[:, j], eo[:, j])
+    z, _ = H.welch_z(eg, eo)
+    assert np.all(np.abs(z) <= 3.0), (z, eg.mean(0), eo.mean(0))

@@ -63,3 +63,23 @@ def test_sample_points_cover_the_domain():
     U = np.array([a for a, _ in pts])
     p = np.array([b for _, b in pts])
     assert U.min() >= 150 and U.max() <= 350 and p.min() >= 15 and p.max() <= 40
+
+
+def test_settle_cycles_needs_every_later_average_inside_the_band():
+    ng = 8
+    ref = np.ones((3, ng + 1))
+    # windows 1..16 (cycles 10..160): far, then within 2 %, a 60 % excursion in window 8, then within 1 %
+    levels = [2.0, 1.6, 1.3, 1.02, 1.02, 1.02, 1.02, 1.6] + [1.01] * 8
+    q = np.array([ref * v for v in levels])
+    # the 5-window averages holding an early window or the excursion lie outside 5 %; from the
+    # average of windows 9-13 on they all lie inside: cycle 130
+    assert W.settle_cycles(q, ref) == 130
+    assert W.settle_cycles(q[:12], ref) is None                               # ends on the excursion
+    assert W.settle_cycles(np.array([ref * 1.2] * 10), ref) is None          # never inside the band
+    assert W.settle_cycles(np.array([ref] * 10), ref) == 50                  # earliest: one full average
+
+
+def test_r25_cycles_from_windows():
+    ng = 4
+    q = np.array([np.ones((3, ng + 1)) * v for v in (1.0, 1.5, 1.2, 1.205, 1.21, 1.212, 1.213)])
+    assert W.r25_cycles(q) == 60
