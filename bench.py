@@ -145,9 +145,10 @@ def main():
     ap.add_argument("--sort", choices=("compact", "cell"), default="compact",
                     help="periodic re-ordering: order-preserving compaction or counting sort by cell")
     ap.add_argument("--sort-every", type=int, default=2000)
-    ap.add_argument("--workload", choices=("single", "sweep", "warmstart"), default="single",
+    ap.add_argument("--workload", choices=("single", "sweep", "warmstart", "working"), default="single",
                     help="single: the 4096-cell discharge; sweep: 64 discharges advanced as one batch; "
-                         "warmstart: learned warm start against cold starts")
+                         "warmstart: learned warm start against cold starts; working: the 512-cell "
+                         "discharge, host-enqueued steps against the cycle graph")
     ap.add_argument("--train-runs", type=int, default=256, help="warmstart: training discharges")
     ap.add_argument("--test-runs", type=int, default=16, help="warmstart: held-out discharges")
     ap.add_argument("--members", type=int, default=64, help="sweep: discharges in the batch")
@@ -172,6 +173,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "sweep":
         return sweep(args)
+    if args.workload == "working":
+        return working(args)
     if args.workload == "warmstart":
         return warmstart(args)
     d = I.config(3)
@@ -331,6 +334,78 @@ def sweep(args):
     }
     print(json.dumps(out), flush=True)
     b.close()
+
+
+def working(args):
+    """The 512-cell working-size discharge (L=2.5 cm, U=400 V, p=40 Pa, 6e5
+    superparticles, 2000 steps per rf cycle, ions every 20): with ~1.7e5 pushes per
+    step the launches, not HBM, set the pace, so the same discharge is advanced
+    both ways a caller can: steps enqueued from the host (pic_step) and a
+    one-member batch that replays one HIP graph per rf cycle.  value = pushes per
+    second of the graph path; one bench step = one rf cycle."""
+    import torch
+    from paper_0705_0497_amd import binding as B
+    from paper_0705_0497_amd import inputs as I
+    procs = I.make_processes()
+    d = I.config(2)
+    d = I.config(2, capacities=tuple(40 * c for c in d.species_counts()))   # the discharge grows ~10x
+    stream = torch.cuda.Stream()
+
+    def make():
+        g = B.Discharge(d, procs, stream=stream, sort_kind=B.SORT_COMPACT, sort_every=2000, max_products=1 << 18)
+        g.load_uniform()                     # loads and starts the leapfrog
+        return g
+
+    def timed(advance, sync, g):
+        for c in range(args.warmup):
+            advance()
+        sync()
+        c0 = g.counters()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in range(args.steps):
+            advance()
+            if (c + 1) % 10 == 0:
+                sync()
+                log(f"bench: timed cycle {c + 1}/{args.steps}")
+        sync()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        dc = g.counters() - c0
+        return int(dc[B.C_PUSH:B.C_PUSH + 3].sum()), el
+
+    spc = d.steps_per_cycle
+    g1 = make()
+    p_host, t_host = timed(lambda: g1.step(spc), g1.sync, g1)
+    log(f"bench: host-enqueued steps {p_host / t_host:.3e} pushes/s")
+    g1.close()
+    g2 = make()
+    b = B.Batch([g2], block=512, sort_every=2000, use_graph=True)
+    p_graph, t_graph = timed(lambda: b.step_cycles(1), b.sync, g2)
+    log(f"bench: cycle graph {p_graph / t_graph:.3e} pushes/s")
+    counts = [g2.count(s) for s in range(3)]
+    b.close()
+    g2.close()
+    out = {
+        "metric": "particle-steps/s (push+deposit+MCC); rf cycles to steady state, warm vs cold",
+        "value": p_graph / t_graph,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_graph / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "512-cell O2 CCP, L=2.5 cm, U=400 V, p=40 Pa, 6e5 superparticles",
+                   "step": "one rf cycle = 2000 electron steps, ions every 20",
+                   "path": "one-member batch, one HIP graph per rf cycle",
+                   "host_enqueued": {"value": p_host / t_host, "ms_per_step": 1e3 * t_host / args.steps},
+                   "superparticles_end": counts, "parallelism": "single GPU"},
+    }
+    print(json.dumps(out), flush=True)
 
 
 def warmstart(args):

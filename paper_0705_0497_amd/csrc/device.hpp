@@ -61,10 +61,11 @@ struct Scalars {
   double e0_prev, u_prev;
   unsigned long long abs0_prev[NSP];
   int32_t jvalid;
-  int32_t pad2;
+  uint32_t field_ticket;            // reduction blocks done in k_reduce_field
 };
 
 constexpr int MAXGRID = 2048;      // largest push grid
+constexpr int SORT_GRID = 256;     // most blocks of the cell sort (rows of sortoff)
 
 // Load balance of the electron push: the slot range and the duration of every
 // block in the last two launches (by step parity).  A launch cuts the store so
@@ -159,6 +160,7 @@ struct Sim {
   PairCell *pcell;                 // [ng] pairing records
   int32_t *phist;                  // [ng][256] pairing key bins (zero between ion steps)
   int32_t *sortcnt, *sortbase;     // [ng], [ng]
+  int32_t *sortoff;                // [SORT_GRID][ng]: each sort block's offset inside every cell
   Scalars *sc;
   long long *events;
   int64_t event_cap;

@@ -212,7 +212,9 @@ __device__ T block_exclusive_scan(T v, T *buf, T &total) {
 // fixes D[1/2].  Same linear system as the tridiagonal one, solved by two scans.
 constexpr int FIELD_PER = 9;   // nodes per thread of the field block: (8192 + 1) / 1024 rounded up
 
-template <int BS>
+// COHERENT: the node charges are read with device-coherent loads, for a caller
+// that runs in the same launch as the atomics that summed them.
+template <int BS, bool COHERENT = false>
 __device__ void field_block(const Sim &S, int64_t step, int mode) {
   static_assert(BS * FIELD_PER >= 8193, "the field block holds every node of the largest grid");
   __shared__ long long sI[BS];
@@ -229,7 +231,15 @@ __device__ void field_block(const Sim &S, int64_t step, int mode) {
   for (int u = 0; u < FIELD_PER; ++u) {
     const int j = j0 + u;
     qe[u] = qp[u] = qn[u] = 0ull;
-    if (j < j1) { qe[u] = Qe[j]; qp[u] = Qp[j]; qn[u] = Qn[j]; }
+    if (j < j1) {
+      if (COHERENT) {
+        qe[u] = __hip_atomic_load(Qe + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        qp[u] = __hip_atomic_load(Qp + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        qn[u] = __hip_atomic_load(Qn + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      } else {
+        qe[u] = Qe[j]; qp[u] = Qp[j]; qn[u] = Qn[j];
+      }
+    }
     q[u] = (long long)S.charge[0] * (long long)qe[u] + (long long)S.charge[1] * (long long)qp[u] +
            (long long)S.charge[2] * (long long)qn[u];
   }
@@ -404,6 +414,44 @@ __global__ __launch_bounds__(BS) void k_field(Sim S, int64_t step, int mode) {
   extern __shared__ int dyn_fix[];
   if (blockIdx.x == 0) field_block<BS>(S, step, mode);
   else fixup_block<BS>(S, blockIdx.x - 1, dyn_fix);
+}
+
+// The electron partials into Q and, in the block that finishes last (a
+// ticket), the field of the next step; NSP more blocks assign the product ids.
+// One launch instead of k_reduce + k_field for the steps between two ion steps,
+// where nothing else changes Q in between.  Reduction block r sums rows
+// b = r / nx, r / nx + RY, ... of node column r % nx.
+constexpr int RF_ROWS = 32;
+
+template <int BS>
+__global__ __launch_bounds__(BS) void k_reduce_field(Sim S, int push_grid, int64_t next_step, int nred) {
+  extern __shared__ int dyn_fix[];
+  __shared__ int last;
+  __shared__ int done[BS / 64];
+  const int nn = S.ng + 1;
+  if ((int)blockIdx.x >= nred) {
+    fixup_block<BS>(S, (int)blockIdx.x - nred, dyn_fix);
+    return;
+  }
+  const int nx = (nn + BS - 1) / BS;
+  const int jx = (int)blockIdx.x % nx, y = (int)blockIdx.x / nx;
+  const int j = jx * BS + threadIdx.x;
+  unsigned long long old = 0ull;
+  if (j < nn) {
+    unsigned long long sum = 0ull;
+    for (int b = y; b < push_grid; b += RF_ROWS) sum += S.part[(size_t)b * nn + j];
+    if (sum) old = atomicAdd(&S.Q[j], sum);
+  }
+  // the returned values are used before the barrier: every add of the block has
+  // been performed (device-coherently) before the ticket is taken, with no cache
+  // write-back or invalidation of a release / acquire fence
+  if ((threadIdx.x & 63) == 0) done[threadIdx.x >> 6] = (int)(old >> 63);
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&S.sc->field_ticket, 1u) == (uint32_t)(nred - 1);
+  __syncthreads();
+  if (!last) return;
+  if (threadIdx.x == 0) S.sc->field_ticket = 0u;
+  field_block<BS, true>(S, next_step, 0);
 }
 
 template <int BS>
@@ -1625,8 +1673,13 @@ __global__ __launch_bounds__(BS) void k_meta_solve(Sim S, double weight, double 
 }
 
 // ---------------------------------------------------------------- cell sort
-// Counting sort by cell, dropping dead particles.  Each thread reads GROUP
-// consecutive slots and handles runs of equal cells with one LDS atomic.
+// Counting sort by cell, dropping dead particles.  The count and the scatter
+// cut the store into the same per-block chunks.  k_sort_count counts its chunk
+// per cell (runs of equal cells with one LDS atomic) and takes, per cell, a
+// range for the block with one global atomic on the cell's total; k_sort_scan
+// turns the totals into cell starts.  Every block then owns one contiguous
+// range per cell, which its tiles fill in order, so that the lines of a range
+// are written by one block in quick succession.
 __device__ __forceinline__ void load_w8(const int32_t *wp, int64_t i0, int32_t w[GROUP]) {
   const int4 a = *reinterpret_cast<const int4 *>(wp + i0), b = *reinterpret_cast<const int4 *>(wp + i0 + 4);
   w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w; w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
@@ -1661,8 +1714,8 @@ __global__ __launch_bounds__(BS) void k_sort_count(Sim S, int s) {
   __syncthreads();
   count_runs<BS>(S, s, N, scnt);
   __syncthreads();
-  for (int j = threadIdx.x; j < ng; j += BS)
-    if (scnt[j]) atomicAdd(&S.sortcnt[j], scnt[j]);
+  int32_t *row = S.sortoff + (size_t)blockIdx.x * ng;
+  for (int j = threadIdx.x; j < ng; j += BS) row[j] = scnt[j] ? atomicAdd(&S.sortcnt[j], scnt[j]) : 0;
 }
 
 template <int BS>
@@ -1686,44 +1739,117 @@ __global__ __launch_bounds__(BS) void k_sort_scan(Sim S, int s) {
   }
 }
 
-// scatter into the other buffer; each block reserves one range per cell it holds
-template <int BS>
-__global__ __launch_bounds__(BS) void k_sort_scatter(Sim S, int s, Particles dst) {
-  extern __shared__ int sh_sort[];
-  int *lcnt = sh_sort, *lbase = sh_sort + S.ng;
+// Scatter into the other buffer, a tile of SORT_T particles at a time (all six
+// fields loaded with 64-bit reads).  When the live cells of a tile span at most
+// SORT_NB cells (the usual case: between two sorts an ion crosses a few cells,
+// an electron some tens), the tile is ordered by cell in LDS and written out
+// with consecutive lanes on consecutive slots of the block's cell ranges.  A
+// wider tile (products appended since the last sort) writes each particle
+// where it goes.  Within a cell the order is that of the LDS reservations.
+constexpr int SORT_BS = 1024, SORT_G = 2, SORT_T = SORT_BS * SORT_G, SORT_NB = 1024;
+
+struct SortTile {
+  int32_t w[SORT_T];
+  float off[SORT_T], vx[SORT_T], vy[SORT_T], vz[SORT_T];
+  uint32_t id[SORT_T];
+  int32_t cnt[SORT_NB], start[SORT_NB], base[SORT_NB];
+  int32_t lo[SORT_BS / 64], hi[SORT_BS / 64], scan[SORT_BS / 64];
+};
+
+size_t sort_lds_bytes(const Sim &S) { return sizeof(SortTile) + 2 * sizeof(int32_t) * (size_t)S.ng; }
+
+__global__ __launch_bounds__(SORT_BS) void k_sort_scatter(Sim S, int s, Particles dst) {
+  extern __shared__ __align__(16) unsigned char sort_lds[];
+  SortTile &t = *reinterpret_cast<SortTile *>(sort_lds);
   const int ng = S.ng;
+  int32_t *lbase = reinterpret_cast<int32_t *>(sort_lds + sizeof(SortTile)), *lfill = lbase + ng;
   const int64_t N = (int64_t)S.sc->nsort[s];
   const int64_t chunk = push_chunk(N, gridDim.x);
   const int64_t begin = (int64_t)blockIdx.x * chunk, end = min(N, begin + chunk);
   if (begin >= end) return;
-  for (int j = threadIdx.x; j < ng; j += BS) lcnt[j] = 0;
-  __syncthreads();
-  count_runs<BS>(S, s, N, lcnt);
-  __syncthreads();
-  for (int j = threadIdx.x; j < ng; j += BS) {
-    lbase[j] = lcnt[j] ? atomicAdd(&S.sortbase[j], lcnt[j]) : 0;
-    lcnt[j] = 0;
+  const int32_t *row = S.sortoff + (size_t)blockIdx.x * ng;
+  for (int j = threadIdx.x; j < ng; j += SORT_BS) {
+    lbase[j] = S.sortbase[j] + row[j];
+    lfill[j] = 0;
   }
-  __syncthreads();
   const Particles &P = S.p[s];
-  for (int64_t i0 = begin + (int64_t)GROUP * threadIdx.x; i0 < end; i0 += (int64_t)GROUP * BS) {
-    int32_t w[GROUP];
-    load_w8(P.w, i0, w);
-    const int nv = (int)min((int64_t)GROUP, end - i0);
-    int k = 0;
-    while (k < nv) {
-      if (w[k] < 0) { ++k; continue; }
-      const int c = w[k] & (int32_t)W_CELL;
-      int len = 1;
-      while (k + len < nv && w[k + len] >= 0 && (w[k + len] & (int32_t)W_CELL) == c) ++len;
-      int64_t d = (int64_t)lbase[c] + atomicAdd(&lcnt[c], len);
-      for (int m = k; m < k + len; ++m, ++d) {
-        const int64_t i = i0 + m;
-        dst.w[d] = w[m]; dst.off[d] = P.off[i]; dst.vx[d] = P.vx[i]; dst.vy[d] = P.vy[i]; dst.vz[d] = P.vz[i];
-        dst.id[d] = P.id[i];
-      }
-      k += len;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int64_t tb = begin; tb < end; tb += SORT_T) {
+    const int64_t i0 = tb + (int64_t)SORT_G * threadIdx.x;
+    int32_t w[SORT_G] = {W_DEAD, W_DEAD};
+    float off[SORT_G], vx[SORT_G], vy[SORT_G], vz[SORT_G];
+    uint32_t id[SORT_G];
+    if (i0 < end) {
+      const int2 a = *reinterpret_cast<const int2 *>(P.w + i0);
+      const float2 o = *reinterpret_cast<const float2 *>(P.off + i0), x = *reinterpret_cast<const float2 *>(P.vx + i0),
+                   y = *reinterpret_cast<const float2 *>(P.vy + i0), z = *reinterpret_cast<const float2 *>(P.vz + i0);
+      const uint2 d = *reinterpret_cast<const uint2 *>(P.id + i0);
+      w[0] = a.x; w[1] = i0 + 1 < end ? a.y : W_DEAD;
+      off[0] = o.x; off[1] = o.y; vx[0] = x.x; vx[1] = x.y; vy[0] = y.x; vy[1] = y.y; vz[0] = z.x; vz[1] = z.y;
+      id[0] = d.x; id[1] = d.y;
     }
+    // live cell range of the tile
+    int cl = 0x7FFFFFFF, ch = -1;
+#pragma unroll
+    for (int k = 0; k < SORT_G; ++k)
+      if (w[k] >= 0) { const int c = w[k] & (int32_t)W_CELL; cl = min(cl, c); ch = max(ch, c); }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) { cl = min(cl, __shfl_xor(cl, o, 64)); ch = max(ch, __shfl_xor(ch, o, 64)); }
+    if (lane == 0) { t.lo[wid] = cl; t.hi[wid] = ch; }
+    __syncthreads();                                  // also: lbase / lfill ready, the previous tile done
+#pragma unroll
+    for (int v = 0; v < SORT_BS / 64; ++v) { cl = min(cl, t.lo[v]); ch = max(ch, t.hi[v]); }
+    if (ch >= 0 && ch - cl < SORT_NB) {
+      const int R = ch - cl + 1;
+      for (int j = threadIdx.x; j < R; j += SORT_BS) t.cnt[j] = 0;
+      __syncthreads();
+      int rank[SORT_G];
+      if (w[0] >= 0 && w[1] >= 0 && ((w[0] ^ w[1]) & (int32_t)W_CELL) == 0) {
+        rank[0] = atomicAdd(&t.cnt[(w[0] & (int32_t)W_CELL) - cl], 2);
+        rank[1] = rank[0] + 1;
+      } else {
+#pragma unroll
+        for (int k = 0; k < SORT_G; ++k)
+          if (w[k] >= 0) rank[k] = atomicAdd(&t.cnt[(w[k] & (int32_t)W_CELL) - cl], 1);
+      }
+      __syncthreads();
+      // cell starts in the tile, and where each cell's part goes in the block's range
+      const int j = threadIdx.x;                      // SORT_NB == SORT_BS: one cell per thread
+      const int c = j < R ? t.cnt[j] : 0;
+      int tot;
+      const int run = block_exclusive_scan<SORT_BS, int32_t>(c, t.scan, tot);
+      if (j < R) {
+        t.start[j] = run;
+        t.base[j] = lbase[cl + j] + lfill[cl + j];
+        lfill[cl + j] += c;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < SORT_G; ++k) {
+        if (w[k] < 0) continue;
+        const int pos = t.start[(w[k] & (int32_t)W_CELL) - cl] + rank[k];
+        t.w[pos] = w[k]; t.off[pos] = off[k]; t.vx[pos] = vx[k]; t.vy[pos] = vy[k]; t.vz[pos] = vz[k];
+        t.id[pos] = id[k];
+      }
+      __syncthreads();
+      for (int q = threadIdx.x; q < tot; q += SORT_BS) {
+        const int32_t wq = t.w[q];
+        const int b = (wq & (int32_t)W_CELL) - cl;
+        const int64_t d = (int64_t)t.base[b] + (q - t.start[b]);
+        dst.w[d] = wq; dst.off[d] = t.off[q]; dst.vx[d] = t.vx[q]; dst.vy[d] = t.vy[q]; dst.vz[d] = t.vz[q];
+        dst.id[d] = t.id[q];
+      }
+    } else if (ch >= 0) {
+#pragma unroll
+      for (int k = 0; k < SORT_G; ++k) {
+        if (w[k] < 0) continue;
+        const int c = w[k] & (int32_t)W_CELL;
+        const int64_t d = (int64_t)lbase[c] + atomicAdd(&lfill[c], 1);
+        dst.w[d] = w[k]; dst.off[d] = off[k]; dst.vx[d] = vx[k]; dst.vy[d] = vy[k]; dst.vz[d] = vz[k];
+        dst.id[d] = id[k];
+      }
+    }
+    __syncthreads();                                  // the tile's LDS is reused by the next one
   }
 }
 
@@ -2226,7 +2352,20 @@ hipError_t set_lds_limits(const Sim &S, int block) {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_fixup<FBS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fixup_lds_bytes(S));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_reduce_field<FBS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fixup_lds_bytes(S));
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_sort_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sort_lds_bytes(S));
   return e;
+}
+
+hipError_t launch_reduce_field(const Sim &S, int push_grid, int64_t next_step, hipStream_t st) {
+  const int nred = ((S.ng + 1 + FBS - 1) / FBS) * RF_ROWS;
+  hipLaunchKernelGGL((k_reduce_field<FBS>), dim3(nred + NSP), dim3(FBS), fixup_lds_bytes(S), st, S, push_grid,
+                     next_step, nred);
+  return hipGetLastError();
 }
 
 hipError_t launch_field(const Sim &S, int64_t step, int mode, hipStream_t st) {
@@ -2274,9 +2413,10 @@ hipError_t launch_eion(const Sim &S, int64_t step, int grid, hipStream_t st) {
 }
 
 hipError_t launch_sort(const Sim &S, int s, const Particles &dst, int grid, hipStream_t st) {
-  hipLaunchKernelGGL((k_sort_count<GBS>), dim3(grid), dim3(GBS), sizeof(int) * S.ng, st, S, s);
+  grid = grid < SORT_GRID ? grid : SORT_GRID;      // count and scatter cut the same chunks
+  hipLaunchKernelGGL((k_sort_count<FBS>), dim3(grid), dim3(FBS), sizeof(int) * S.ng, st, S, s);
   hipLaunchKernelGGL((k_sort_scan<FBS>), dim3(1), dim3(FBS), 0, st, S, s);
-  hipLaunchKernelGGL((k_sort_scatter<GBS>), dim3(grid), dim3(GBS), 2 * sizeof(int) * S.ng, st, S, s, dst);
+  hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(SORT_BS), sort_lds_bytes(S), st, S, s, dst);
   return hipGetLastError();
 }
 

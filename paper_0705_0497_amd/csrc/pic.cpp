@@ -24,6 +24,7 @@ hipError_t launch_meta_init(const Sim &S, int tab, hipStream_t st);
 hipError_t launch_meta_solve(const Sim &S, double weight, double tau, double D, double nu_q, double h, hipStream_t st);
 hipError_t launch_eion(const Sim &S, int64_t step, int grid, hipStream_t st);
 hipError_t launch_sort(const Sim &S, int s, const Particles &dst, int grid, hipStream_t st);
+hipError_t launch_reduce_field(const Sim &S, int push_grid, int64_t next_step, hipStream_t st);
 hipError_t launch_diag(const Sim &S, int s, int grid, hipStream_t st);
 hipError_t launch_load(const Sim &S, int s, int64_t count, float vth, int grid, hipStream_t st);
 hipError_t launch_shift(const Sim &S, int s, int grid, hipStream_t st);
@@ -64,7 +65,7 @@ struct Layout {
   size_t total = 0;
   size_t part[NSP][2][6];   // two buffers x (w, off, vx, vy, vz, id)
   size_t pkey[NSP], pbkt[NSP], ptmp[NSP], bcnt;
-  size_t Q, E, phi, sumQ, sumphi, esum, ecnt, edf, iedf, nacc, kleft, pcell, phist, sortcnt, sortbase, sc, sigma,
+  size_t Q, E, phi, sumQ, sumphi, esum, ecnt, edf, iedf, nacc, kleft, pcell, phist, sortcnt, sortbase, sortoff, sc, sigma,
       hbound, events, partials, ttot, blkcnt, prof, jsum, jcnt, jpow, kleft_neg, dens_ei, meta_src, na, na_f,
       meta_tmp, bal;
   size_t take(size_t bytes) {
@@ -101,6 +102,7 @@ Layout make_layout(const pic_config &c, const pic_species *sp, int nproc) {
   L.phist = L.take(4 * (size_t)256 * c.ng);
   L.sortcnt = L.take(4 * (size_t)c.ng);
   L.sortbase = L.take(4 * (size_t)c.ng);
+  L.sortoff = L.take(4 * (size_t)SORT_GRID * c.ng);
   L.sc = L.take(sizeof(Scalars));
   L.sigma = L.take(4 * (size_t)nproc * c.table_n);
   L.hbound = L.take(8 * (size_t)nproc * (c.table_n - 1));
@@ -203,6 +205,7 @@ struct pic_handle {
   int block = 512, grid[NSP] = {1, 1, 1}, hgrid = 1, pgrid = 1;
   int ncu = 1;
   bool batch_busy = false;         // stepped by a batch that has not been synchronised
+  bool field_ready = false;        // the field of `step` was solved by the previous step's reduction
   std::string err;
   // spatially resolved O2(a): configuration and the step its tally window began
   bool meta_on = false;
@@ -444,6 +447,7 @@ int pic_create(const pic_config *cfg, const pic_species *sp, const pic_process *
   S.sortcnt = (int32_t *)(ws + L.sortcnt);
   S.bcnt = (int32_t *)(ws + L.bcnt);
   S.sortbase = (int32_t *)(ws + L.sortbase);
+  S.sortoff = (int32_t *)(ws + L.sortoff);
   S.sc = (Scalars *)(ws + L.sc);
   S.sigma = (const float *)(ws + L.sigma);
   S.hbound = (const double *)(ws + L.hbound);
@@ -789,14 +793,19 @@ int pic_get_step(pic_handle *h, int64_t *step) {
   return PIC_OK;
 }
 
-static int enqueue_step(pic_handle *h, hipEvent_t ev0, hipEvent_t ev1) {
+// One step.  `more`: the caller enqueues the next step right after this one;
+// then, when neither this step nor the next moves ions, the electron reduction
+// also solves the next step's field (h->field_ready), so that state read
+// between pic_step calls is never ahead of the step index.
+static int enqueue_step(pic_handle *h, hipEvent_t ev0, hipEvent_t ev1, bool more) {
   Sim &S = h->S;
   const pic_config &c = h->cfg;
   const int64_t n = h->step;
   // electron-ion channels: the ion densities of this step's field, before it clears them
   const bool eion = S.nei > 0 && !(S.flags & F_NO_COLL) && n % c.ksub == 0;
   if (eion) HIPCHK(h, launch_eiprep(S, h->stream));
-  HIPCHK(h, launch_field(S, n, 0, h->stream));
+  if (!h->field_ready) HIPCHK(h, launch_field(S, n, 0, h->stream));
+  h->field_ready = false;
   if (c.diag_every > 0 && n % c.diag_every == 0)
     for (int s = 0; s < NSP; ++s) HIPCHK(h, launch_diag(S, s, h->hgrid, h->stream));
   if (c.sort_every > 0 && n % c.sort_every == 0) {
@@ -812,7 +821,9 @@ static int enqueue_step(pic_handle *h, hipEvent_t ev0, hipEvent_t ev1) {
   if (ev0) HIPCHK(h, hipEventRecord(ev0, h->stream));
   HIPCHK(h, launch_push(S, 0, n, h->grid[0], h->block, h->stream));
   if (ev1) HIPCHK(h, hipEventRecord(ev1, h->stream));
-  HIPCHK(h, launch_reduce(S, 0, h->grid[0], h->stream));
+  const bool fuse = more && n % c.ksub != 0 && (n + 1) % c.ksub != 0;
+  if (fuse) HIPCHK(h, launch_reduce_field(S, h->grid[0], n + 1, h->stream));
+  else HIPCHK(h, launch_reduce(S, 0, h->grid[0], h->stream));
   if (eion) HIPCHK(h, launch_eion(S, n, h->hgrid, h->stream));
   if (n % c.ksub == 0) {
     HIPCHK(h, launch_push(S, 1, n, h->grid[1], h->block, h->stream));
@@ -826,6 +837,7 @@ static int enqueue_step(pic_handle *h, hipEvent_t ev0, hipEvent_t ev1) {
       for (int stage = 0; stage < 4; ++stage) HIPCHK(h, launch_pair(S, n, stage, 2, h->pgrid, h->stream));
   }
   h->step = n + 1;
+  h->field_ready = fuse;
   return PIC_OK;
 }
 
@@ -833,7 +845,7 @@ int pic_step(pic_handle *h, int64_t n_steps) {
   if (!h || n_steps < 0) return PIC_EINVAL;
   if (h->batch_busy) return fail(h, PIC_EBUSY, "member of a batch with unsynchronised work (call pic_batch_sync)");
   for (int64_t k = 0; k < n_steps; ++k) {
-    const int r = enqueue_step(h, nullptr, nullptr);
+    const int r = enqueue_step(h, nullptr, nullptr, k + 1 < n_steps);
     if (r != PIC_OK) return r;
   }
   return PIC_OK;
@@ -853,7 +865,7 @@ int pic_step_timed(pic_handle *h, int64_t n_steps, double *ms_push_e, double *ms
   HIPCHK(h, hipEventRecord(t0, h->stream));
   for (int64_t k = 0; k < n_steps && rc == PIC_OK;) {
     const int m = (int)std::min<int64_t>(CH, n_steps - k);
-    for (int j = 0; j < m && rc == PIC_OK; ++j) rc = enqueue_step(h, ev[2 * j], ev[2 * j + 1]);
+    for (int j = 0; j < m && rc == PIC_OK; ++j) rc = enqueue_step(h, ev[2 * j], ev[2 * j + 1], k + j + 1 < n_steps);
     if (rc != PIC_OK) break;
     HIPCHK(h, hipEventSynchronize(ev[2 * m - 1]));
     for (int j = 0; j < m; ++j) {

@@ -203,6 +203,31 @@ def test_determinism_across_repeats_blocks_and_sort_interval():
     np.testing.assert_array_equal(qa, qf)
 
 
+def test_multi_step_calls_equal_single_steps():
+    """pic_step(h, n) solves the field of each next electron-only step inside the
+    electron reduction; n calls of one step never do.  Both reach the same state,
+    field, moments and counters bit for bit, at two grid sizes (one and several
+    node columns of the reduction)."""
+    from paper_0705_0497_amd.binding import Discharge
+    for d in (I.config(1), I.config(1, ng=2500, n_total=60000)):
+        procs = H.neutralising(I.make_processes())
+        a = Discharge(d, procs)
+        b = Discharge(d, procs)
+        a.load_uniform()
+        b.load_uniform()
+        a.step(157)
+        for _ in range(157):
+            b.step(1)
+        _same([H.by_id(a.get_particles(s)[0]) for s in range(3)], [H.by_id(b.get_particles(s)[0]) for s in range(3)])
+        np.testing.assert_array_equal(a.hist(), b.hist())
+        for x, y in zip(a.field(), b.field()):
+            np.testing.assert_array_equal(x, y)
+        ma, mb = a.moments(), b.moments()
+        for k in ma:
+            np.testing.assert_array_equal(ma[k], mb[k], err_msg=k)
+        np.testing.assert_array_equal(a.counters(), b.counters())
+
+
 def test_resume_is_bitwise():
     from paper_0705_0497_amd.binding import Discharge
     d = I.config(1)
