@@ -23,23 +23,18 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-BYTES_PUSH = 24          # read + write cell word, offset, vx
-BYTES_CAND = 12          # read id, vy, vz at the end of a free flight (the energy for the null test)
-BYTES_REDRAW = 4         # read id at the end of a capped flight (a new flight only)
-BYTES_SCATTER = 8        # write vy, vz after an electron collision that changes the velocity
-BYTES_PRODUCT = 24       # one new particle record
+BYTES_PUSH = 24          # read + write the position (cell word, offset) and vx
+BYTES_CAND = 20          # at a collision candidate (a free-flight end): read id, read + write vy, vz
 HBM_PEAK_GBS = 8000.0    # MI355X HBM3E
 
 
-def push_alg_bytes(dc, procs):
-    """Algorithmic HBM bytes of the electron push over a counter difference dc: the
-    least any electron push with this MCC has to move (the per-unit figures above)."""
+def push_alg_bytes(dc, procs=None):
+    """Algorithmic HBM bytes of the electron push over a counter difference dc:
+    24 B per push and 20 B per collision candidate, the per-unit figures of the
+    streaming sweep this MCC has to make (the amortised re-ordering bytes belong
+    to the sort kernels, not to this one)."""
     from paper_0705_0497_amd import binding as B
-    ev = lambda kinds: sum(int(dc[B.C_EVENT + i]) for i, p in enumerate(procs)
-                           if p.species == 0 and p.kind in kinds)
-    born = 2 * ev(("ionize",)) + ev(("attach",))           # products written by the electron kernel
-    return (BYTES_PUSH * int(dc[B.C_PUSH]) + BYTES_CAND * int(dc[B.C_CAND]) + BYTES_REDRAW * int(dc[B.C_REDRAW])
-            + BYTES_SCATTER * ev(("elastic", "excite", "ionize")) + BYTES_PRODUCT * born)
+    return BYTES_PUSH * int(dc[B.C_PUSH]) + BYTES_CAND * int(dc[B.C_CAND])
 
 
 def log(*a):
@@ -145,10 +140,10 @@ def main():
     ap.add_argument("--sort", choices=("compact", "cell"), default="compact",
                     help="periodic re-ordering: order-preserving compaction or counting sort by cell")
     ap.add_argument("--sort-every", type=int, default=2000)
-    ap.add_argument("--workload", choices=("single", "sweep", "warmstart", "working"), default="single",
+    ap.add_argument("--workload", choices=("single", "sweep", "warmstart", "working", "mlp"), default="single",
                     help="single: the 4096-cell discharge; sweep: 64 discharges advanced as one batch; "
                          "warmstart: learned warm start against cold starts; working: the 512-cell "
-                         "discharge, host-enqueued steps against the cycle graph")
+                         "discharge, host-enqueued steps against the cycle graph; mlp: the network kernels alone")
     ap.add_argument("--train-runs", type=int, default=256, help="warmstart: training discharges")
     ap.add_argument("--test-runs", type=int, default=16, help="warmstart: held-out discharges")
     ap.add_argument("--members", type=int, default=64, help="sweep: discharges in the batch")
@@ -175,6 +170,8 @@ def main():
         return sweep(args)
     if args.workload == "working":
         return working(args)
+    if args.workload == "mlp":
+        return mlp(args)
     if args.workload == "warmstart":
         return warmstart(args)
     d = I.config(3)
@@ -381,6 +378,9 @@ def working(args):
     g1.close()
     g2 = make()
     b = B.Batch([g2], block=512, sort_every=2000, use_graph=True)
+    tune = b.autotune(window=200)                 # block size and re-ordering interval, ~1 rf cycle of trials
+    b.sync()
+    log(f"bench: autotune -> {tune['best']}")
     p_graph, t_graph = timed(lambda: b.step_cycles(1), b.sync, g2)
     log(f"bench: cycle graph {p_graph / t_graph:.3e} pushes/s")
     counts = [g2.count(s) for s in range(3)]
@@ -401,11 +401,71 @@ def working(args):
         "data": "synthetic",
         "config": {"workload": "512-cell O2 CCP, L=2.5 cm, U=400 V, p=40 Pa, 6e5 superparticles",
                    "step": "one rf cycle = 2000 electron steps, ions every 20",
-                   "path": "one-member batch, one HIP graph per rf cycle",
+                   "path": "one-member batch, one HIP graph per rf cycle", "autotuned": tune["best"],
                    "host_enqueued": {"value": p_host / t_host, "ms_per_step": 1e3 * t_host / args.steps},
                    "superparticles_end": counts, "parallelism": "single GPU"},
     }
     print(json.dumps(out), flush=True)
+
+
+def mlp(args):
+    """The warm-start network's kernels alone: one training step (forward,
+    backward, Adam) on batches of 8192 of a synthetic training set of the
+    learned part's size (256 discharges x 512 points, inputs (U, log p, x/L),
+    smooth targets), then forward passes over the whole set.  value = training
+    samples per second; the roofline is MFMA bf16 on the counted multiply-adds
+    (2 flops each: 3.98e5 per sample forward, twice that backward)."""
+    import numpy as np
+    import torch
+    from paper_0705_0497_amd import binding as B
+    from paper_0705_0497_amd import warmstart as W
+    rng = np.random.Generator(np.random.PCG64(17))
+    pts = W.sample_points(256, 13)
+    X = np.concatenate([W.features(U, p) for U, p in pts])
+    a = rng.standard_normal((1, 6)).astype(np.float32)
+    T = np.tanh(X[:, :1] * a + np.sin(3.0 * X[:, 2:3] + X[:, 1:2] * a)).astype(np.float32)
+    Xd = torch.from_numpy(X).cuda()
+    Td = torch.from_numpy(T).cuda()
+    batch = 8192
+    net = B.Network(batch, params=W.init_params(0))
+    n = len(X)
+    flop_fwd = 2.0 * (3 * 256 + 3 * 256 * 256 + 256 * 6)
+
+    def epoch():
+        for b0 in range(0, n, batch):
+            net.backward(Xd[b0:b0 + batch], Td[b0:b0 + batch], want_loss=False)
+            net.adam(1e-3)
+
+    for _ in range(args.warmup):
+        epoch()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        epoch()
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    steps = args.steps * ((n + batch - 1) // batch)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        net.forward(Xd)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    rate = args.steps * n / t_train
+    tflops = 3.0 * flop_fwd * rate / 1e12
+    out = {
+        "metric": "training samples/s of the warm-start network (forward + backward + Adam)",
+        "value": rate, "unit": "samples/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * t_train / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "MLP 3 -> 4 x 256 GELU -> 6, batches of 8192 over 256 x 512 samples",
+                   "step": "one epoch (16 training steps)", "training_step_us": 1e6 * t_train / steps,
+                   "forward_samples_per_s": args.steps * n / t_fwd, "parallelism": "single GPU"},
+        "roofline": {"bound": "mfma", "achieved": tflops, "peak": 2500.0, "unit": "TFLOP/s",
+                     "frac": tflops / 2500.0, "traffic": None,
+                     "kernel": "training step (all network kernels over wall time)"},
+    }
+    print(json.dumps(out), flush=True)
+    net.close()
 
 
 def warmstart(args):
@@ -420,7 +480,7 @@ def warmstart(args):
     from paper_0705_0497_amd import warmstart as W
     t0 = time.perf_counter()
     r = W.experiment(W.sample_points(args.train_runs, 11), W.sample_points(args.test_runs, 12),
-                     n_total=100000, train_horizon=1600, horizon=2500, late=400, epochs=1500, reference=True,
+                     n_total=30000, horizon=3000, late=500, epochs=1500, reference=True,
                      log=lambda m: log(f"bench: [{time.perf_counter() - t0:5.0f} s] {m}"))
     rows = r["rows"]
     cold = [x["cold_cycles"] for x in rows]
@@ -438,7 +498,8 @@ def warmstart(args):
         "ms_per_step": 1e3 * r["seconds"]["eval"] / r["eval_cycles"],
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
         "config": {"workload": f"learned warm start: {args.train_runs} training + {args.test_runs} held-out "
-                               "128-cell O2 CCP discharges (L=2.5 cm, U 150-350 V, p 15-40 Pa, 1e5 superparticles)",
+                               "128-cell O2 CCP discharges (L=2.5 cm, U 200-350 V, p 12-17 Pa log-uniform, "
+                               "3e4 superparticles loaded, every run to 3000 rf cycles)",
                    "step": "one rf cycle of the evaluation batch (cold, warm and reference members together)",
                    "horizon_cycles": r["horizon"], "late_average_cycles": r["late"],
                    "train_horizon_cycles": r["train_horizon"],

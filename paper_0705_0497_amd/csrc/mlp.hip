@@ -40,7 +40,8 @@ __device__ __forceinline__ float gelu_prime(float z) {
 // ---------------------------------------------------------------- tiled product
 // C[m][n] = sum_k A(m, k) B(k, n), A(m, k) = A[m sam + k sak], B(k, n) = B[k sbk + n sbn]
 // (bfloat16), FP32 sums on the matrix cores.  A block of 4 waves owns a 64 x 64
-// tile; each wave a 32 x 32 quarter as 2 x 2 products of v_mfma_f32_16x16x32_bf16.
+// tile; each wave a 32 x 32 quarter as 2 x 2 products of v_mfma_f32_16x16x32_bf16,
+// k taken TK at a time through LDS and 32 at a time through the matrix cores.
 // blockIdx.z selects a K range of kchunk (split-K partials).
 enum { EPI_STORE = 0, EPI_HIDDEN = 1, EPI_OUT = 2, EPI_BWD = 3 };
 
@@ -57,6 +58,48 @@ struct GemmArgs {
 };
 
 constexpr int TM = 64, TN = 64, TK = 32, TKP = TK + 8;   // LDS rows padded by 16 bytes
+constexpr int TV = TM * TK / 8 / 256;                      // 16-byte vectors per thread and tile
+
+// The 64 x TK tile T[r][k] = X(r0 + r, k0 + k), X(r, k) = P[r sr + k sk], zero
+// outside r < R, k < ke.  Along whichever index is contiguous in memory each
+// thread moves 8 elements with one 16-byte load when they are in range and
+// aligned (k contiguous: activations and weights of the forward pass and of the
+// input gradient; r contiguous: the output gradients of the weight gradient).
+__device__ __forceinline__ void load_tile(__bf16 (*T)[TKP], const __bf16 *P, int64_t sr, int64_t sk, int r0, int R,
+                                          int k0, int ke, int t) {
+  const __bf16 zero = (__bf16)0.0f;
+  constexpr int KV = TK / 8;                     // vectors along k per row
+  for (int v = 0; v < TV; ++v) {
+    const int q = v * 256 + t;                   // vector index in the tile
+    if (sk == 1) {
+      const int lr = q / KV, lk = (q % KV) * 8;
+      const int r = r0 + lr, k = k0 + lk;
+      const __bf16 *src = P + (int64_t)r * sr + k;
+      if (r < R && k + 8 <= ke && ((uintptr_t)src & 15) == 0) {
+        *reinterpret_cast<bf16x8 *>(&T[lr][lk]) = *reinterpret_cast<const bf16x8 *>(src);
+      } else {
+        for (int i = 0; i < 8; ++i) T[lr][lk + i] = (r < R && k + i < ke) ? src[i] : zero;
+      }
+    } else if (sr == 1) {
+      const int lk = q / (TM / 8), lr = (q % (TM / 8)) * 8;
+      const int r = r0 + lr, k = k0 + lk;
+      const __bf16 *src = P + r + (int64_t)k * sk;
+      if (k < ke && r + 8 <= R && ((uintptr_t)src & 15) == 0) {
+        const bf16x8 x = *reinterpret_cast<const bf16x8 *>(src);
+        for (int i = 0; i < 8; ++i) T[lr + i][lk] = x[i];
+      } else {
+        for (int i = 0; i < 8; ++i) T[lr + i][lk] = (k < ke && r + i < R) ? src[i] : zero;
+      }
+    } else {
+      const int lr = q / KV, lk = (q % KV) * 8;
+      const int r = r0 + lr;
+      for (int i = 0; i < 8; ++i) {
+        const int k = k0 + lk + i;
+        T[lr][lk + i] = (r < R && k < ke) ? P[(int64_t)r * sr + (int64_t)k * sk] : zero;
+      }
+    }
+  }
+}
 
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
@@ -69,28 +112,20 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   floatx4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.0f, 0.0f, 0.0f, 0.0f};
-  const int lr = t >> 2, lk = (t & 3) * 8;          // this thread's row / column and 8 k values
-  const __bf16 zero = (__bf16)0.0f;
   for (int k0 = kb; k0 < ke; k0 += TK) {
-    {
-      const int m = m0 + lr;
-      for (int i = 0; i < 8; ++i) {
-        const int k = k0 + lk + i;
-        As[lr][lk + i] = (m < g.M && k < ke) ? g.A[(int64_t)m * g.sam + (int64_t)k * g.sak] : zero;
-      }
-      const int n = n0 + lr;
-      for (int i = 0; i < 8; ++i) {
-        const int k = k0 + lk + i;
-        Bs[lr][lk + i] = (n < g.N && k < ke) ? g.B[(int64_t)k * g.sbk + (int64_t)n * g.sbn] : zero;
-      }
-    }
+    load_tile(As, g.A, g.sam, g.sak, m0, g.M, k0, ke, t);
+    load_tile(Bs, g.B, g.sbn, g.sbk, n0, g.N, k0, ke, t);
     __syncthreads();
     const int kq = 8 * (lane >> 4), rr = lane & 15;
-    bf16x8 a[2], b[2];
-    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[wr * 32 + i * 16 + rr][kq]);
-    for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wc * 32 + j * 16 + rr][kq]);
-    for (int i = 0; i < 2; ++i)
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    const int ksub = min(TK, ke - k0);             // products of 32 k values in order, as many as the tile holds
+    for (int kk = 0; kk < ksub; kk += 32) {
+      bf16x8 a[2], b[2];
+      for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8 *>(&As[wr * 32 + i * 16 + rr][kk + kq]);
+      for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8 *>(&Bs[wc * 32 + j * 16 + rr][kk + kq]);
+      for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
     __syncthreads();
   }
   // result layout of a 16 x 16 product: lane l holds rows 4 (l / 16) + v, column l % 16
@@ -159,18 +194,18 @@ __global__ __launch_bounds__(256) void k_loss_sum(const float *part, int nb, flo
 }
 
 // bias gradient: column sums of dz [rows][cols], one block per column, fixed order
-__global__ __launch_bounds__(256) void k_colsum(const float *dz, int64_t rows, int cols, float *out) {
-  __shared__ float red[256];
-  const int c = blockIdx.x;
-  float s = 0.0f;
-  for (int64_t r = threadIdx.x; r < rows; r += 256) s += dz[r * cols + c];
-  red[threadIdx.x] = s;
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
-    __syncthreads();
+// bias gradients, first pass: block b sums rows [b rchunk, (b + 1) rchunk) of
+// every column (consecutive threads on consecutive columns of a row) into
+// part[b][c]; k_sum_splits adds the blocks in order
+constexpr int COLSUM_ROWS = 32;
+
+__global__ __launch_bounds__(256) void k_colsum_part(const float *dz, int64_t rows, int cols, float *part) {
+  const int64_t r0 = (int64_t)blockIdx.x * COLSUM_ROWS, r1 = min(rows, r0 + COLSUM_ROWS);
+  for (int c = threadIdx.x; c < cols; c += 256) {
+    float s = 0.0f;
+    for (int64_t r = r0; r < r1; ++r) s += dz[r * cols + c];
+    part[(int64_t)blockIdx.x * cols + c] = s;
   }
-  if (threadIdx.x == 0) out[c] = red[0];
 }
 
 __global__ void k_sum_splits(const float *part, int nsplit, int64_t n, float *out) {
@@ -224,7 +259,9 @@ Layout make_layout(int64_t B) {
     L.dz32[k] = L.take(4 * (size_t)B * MLP_NHID);
     L.dz16[k] = L.take(2 * (size_t)B * MLP_NHID);
   }
-  L.part = L.take(4 * (size_t)MAXSPLIT * MLP_NHID * MLP_NHID);
+  // split-K partials of a weight gradient, or the row-block partials of a bias gradient
+  L.part = L.take(4 * std::max<size_t>((size_t)MAXSPLIT * MLP_NHID * MLP_NHID,
+                                       (size_t)((B + COLSUM_ROWS - 1) / COLSUM_ROWS) * MLP_NHID));
   L.lossp = L.take(4 * LOSS_BLOCKS);
   L.loss = L.take(4);
   return L;
@@ -479,7 +516,11 @@ int mlp_backward(mlp_handle *h, int32_t batch, const float *x, const float *t, f
     hipLaunchKernelGGL(k_sum_splits, dim3(grid_of(nw)), dim3(256), 0, st, h->at<float>(L.part), split, nw,
                        h->at<float>(L.g) + w_off(l));
     MHIP(h, hipGetLastError());
-    hipLaunchKernelGGL(k_colsum, dim3(out), dim3(256), 0, st, h->at<float>(L.dz32[cur]), (int64_t)batch, out,
+    const int nrb = (batch + COLSUM_ROWS - 1) / COLSUM_ROWS;     // the partials reuse the split-K buffer
+    hipLaunchKernelGGL(k_colsum_part, dim3(nrb), dim3(256), 0, st, h->at<float>(L.dz32[cur]), (int64_t)batch, out,
+                       h->at<float>(L.part));
+    MHIP(h, hipGetLastError());
+    hipLaunchKernelGGL(k_sum_splits, dim3(grid_of(out)), dim3(256), 0, st, h->at<float>(L.part), nrb, (int64_t)out,
                        h->at<float>(L.g) + b_off(l));
     MHIP(h, hipGetLastError());
     if (l == 0) break;

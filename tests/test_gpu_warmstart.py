@@ -3,8 +3,8 @@ on the GPU (BF16 MFMA kernels) from the steady-state profiles of batched cold
 runs loads held-out discharges close to their steady state.  Cold and warm runs
 go on to a common horizon; the steady state is the cold run's late average, and
 a run has reached it when every 50-cycle average of its e and O2+ densities
-stays within 5 % of it.  Small version of the benchmark experiment (8 training
-runs, 2 held-out points)."""
+stays within 5 % of it.  Small version of the benchmark experiment (9 training
+runs, 2 held-out points, 2000 cycles)."""
 import pytest
 
 pytestmark = pytest.mark.gpu
@@ -12,9 +12,9 @@ pytestmark = pytest.mark.gpu
 
 def test_warm_start_reaches_the_same_state_in_fewer_cycles():
     from paper_0705_0497_amd import warmstart as W
-    train = [(U, p) for U in (160.0, 230.0, 300.0) for p in (15.0, 28.0)] + [(195.0, 20.0), (265.0, 20.0)]
-    test = [(210.0, 18.0), (250.0, 24.0)]
-    r = W.experiment(train, test, n_total=100000, train_horizon=1600, horizon=2000, late=400, epochs=1500,
+    train = [(U, p) for U in (220.0, 250.0, 280.0) for p in (13.0, 14.0, 15.0)]
+    test = [(235.0, 13.5), (265.0, 14.5)]
+    r = W.experiment(train, test, n_total=40000, horizon=2000, late=400, epochs=1500,
                      log=lambda m: print("warm start:", m, flush=True))
     assert r["loss"][-1][1] < 0.05 * r["loss"][0][1]
     for row in r["rows"]:

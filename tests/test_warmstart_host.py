@@ -62,7 +62,9 @@ def test_sample_points_cover_the_domain():
     pts = W.sample_points(200, 3)
     U = np.array([a for a, _ in pts])
     p = np.array([b for _, b in pts])
-    assert U.min() >= 150 and U.max() <= 350 and p.min() >= 15 and p.max() <= 40
+    assert U.min() >= 200 and U.max() <= 350 and p.min() >= 12 and p.max() <= 17
+    # p log-uniform: as many points below the geometric mean of the range as above
+    assert abs(int(np.sum(p < np.sqrt(12.0 * 17.0))) - 100) < 30
 
 
 def test_settle_cycles_needs_every_later_average_inside_the_band():
