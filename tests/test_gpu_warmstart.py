@@ -12,8 +12,10 @@ pytestmark = pytest.mark.gpu
 
 def test_warm_start_reaches_the_same_state_in_fewer_cycles():
     from paper_0705_0497_amd import warmstart as W
-    train = [(U, p) for U in (220.0, 250.0, 280.0) for p in (13.0, 14.0, 15.0)]
-    test = [(235.0, 13.5), (265.0, 14.5)]
+    # held-out points inside a 3 x 3 grid of training points (15 V, 0.5 Pa apart): the density
+    # changes by ~30 % per Pa here, so a coarser grid leaves the prediction several % off
+    train = [(U, p) for U in (225.0, 240.0, 255.0) for p in (13.0, 13.5, 14.0)]
+    test = [(232.0, 13.25), (248.0, 13.75)]
     r = W.experiment(train, test, n_total=40000, horizon=2000, late=400, epochs=1500,
                      log=lambda m: print("warm start:", m, flush=True))
     assert r["loss"][-1][1] < 0.05 * r["loss"][0][1]
