@@ -194,18 +194,18 @@ __global__ __launch_bounds__(256) void k_loss_sum(const float *part, int nb, flo
 }
 
 // bias gradient: column sums of dz [rows][cols], one block per column, fixed order
-// bias gradients, first pass: block b sums rows [b rchunk, (b + 1) rchunk) of
-// every column (consecutive threads on consecutive columns of a row) into
-// part[b][c]; k_sum_splits adds the blocks in order
-constexpr int COLSUM_ROWS = 32;
-
-__global__ __launch_bounds__(256) void k_colsum_part(const float *dz, int64_t rows, int cols, float *part) {
-  const int64_t r0 = (int64_t)blockIdx.x * COLSUM_ROWS, r1 = min(rows, r0 + COLSUM_ROWS);
-  for (int c = threadIdx.x; c < cols; c += 256) {
-    float s = 0.0f;
-    for (int64_t r = r0; r < r1; ++r) s += dz[r * cols + c];
-    part[(int64_t)blockIdx.x * cols + c] = s;
+__global__ __launch_bounds__(256) void k_colsum(const float *dz, int64_t rows, int cols, float *out) {
+  __shared__ float red[256];
+  const int c = blockIdx.x;
+  float s = 0.0f;
+  for (int64_t r = threadIdx.x; r < rows; r += 256) s += dz[r * cols + c];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) out[c] = red[0];
 }
 
 __global__ void k_sum_splits(const float *part, int nsplit, int64_t n, float *out) {
@@ -259,9 +259,7 @@ Layout make_layout(int64_t B) {
     L.dz32[k] = L.take(4 * (size_t)B * MLP_NHID);
     L.dz16[k] = L.take(2 * (size_t)B * MLP_NHID);
   }
-  // split-K partials of a weight gradient, or the row-block partials of a bias gradient
-  L.part = L.take(4 * std::max<size_t>((size_t)MAXSPLIT * MLP_NHID * MLP_NHID,
-                                       (size_t)((B + COLSUM_ROWS - 1) / COLSUM_ROWS) * MLP_NHID));
+  L.part = L.take(4 * (size_t)MAXSPLIT * MLP_NHID * MLP_NHID);
   L.lossp = L.take(4 * LOSS_BLOCKS);
   L.loss = L.take(4);
   return L;
@@ -516,11 +514,7 @@ int mlp_backward(mlp_handle *h, int32_t batch, const float *x, const float *t, f
     hipLaunchKernelGGL(k_sum_splits, dim3(grid_of(nw)), dim3(256), 0, st, h->at<float>(L.part), split, nw,
                        h->at<float>(L.g) + w_off(l));
     MHIP(h, hipGetLastError());
-    const int nrb = (batch + COLSUM_ROWS - 1) / COLSUM_ROWS;     // the partials reuse the split-K buffer
-    hipLaunchKernelGGL(k_colsum_part, dim3(nrb), dim3(256), 0, st, h->at<float>(L.dz32[cur]), (int64_t)batch, out,
-                       h->at<float>(L.part));
-    MHIP(h, hipGetLastError());
-    hipLaunchKernelGGL(k_sum_splits, dim3(grid_of(out)), dim3(256), 0, st, h->at<float>(L.part), nrb, (int64_t)out,
+    hipLaunchKernelGGL(k_colsum, dim3(out), dim3(256), 0, st, h->at<float>(L.dz32[cur]), (int64_t)batch, out,
                        h->at<float>(L.g) + b_off(l));
     MHIP(h, hipGetLastError());
     if (l == 0) break;
