@@ -473,14 +473,14 @@ def warmstart(args):
     long horizon (their late average), the network trained on the GPU, then every
     held-out (U, p) run cold, warm and cold again (other random streams) in one
     batch to a common horizon.  value = particle-steps/s of that evaluation batch;
-    the rf cycles to the steady state (the cold run's late average: every 50-cycle
+    the rf cycles to the steady state (the cold run's late average: every 100-cycle
     average of e and O2+ within 5 % from then on), cold and warm, and the profile
     errors are in config; the earlier 1 %-per-20-cycles test is reported beside."""
     import numpy as np
     from paper_0705_0497_amd import warmstart as W
     t0 = time.perf_counter()
     r = W.experiment(W.sample_points(args.train_runs, 11), W.sample_points(args.test_runs, 12),
-                     n_total=30000, horizon=3000, late=500, epochs=1500, reference=True,
+                     n_total=40000, horizon=3000, late=500, epochs=1500, reference=True,
                      log=lambda m: log(f"bench: [{time.perf_counter() - t0:5.0f} s] {m}"))
     rows = r["rows"]
     cold = [x["cold_cycles"] for x in rows]
@@ -499,7 +499,7 @@ def warmstart(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
         "config": {"workload": f"learned warm start: {args.train_runs} training + {args.test_runs} held-out "
                                "128-cell O2 CCP discharges (L=2.5 cm, U 200-350 V, p 12-17 Pa log-uniform, "
-                               "3e4 superparticles loaded, every run to 3000 rf cycles)",
+                               "4e4 superparticles loaded, every run to 3000 rf cycles)",
                    "step": "one rf cycle of the evaluation batch (cold, warm and reference members together)",
                    "horizon_cycles": r["horizon"], "late_average_cycles": r["late"],
                    "train_horizon_cycles": r["train_horizon"],

@@ -2,7 +2,7 @@
 on the GPU (BF16 MFMA kernels) from the steady-state profiles of batched cold
 runs loads held-out discharges close to their steady state.  Cold and warm runs
 go on to a common horizon; the steady state is the cold run's late average, and
-a run has reached it when every 50-cycle average of its e and O2+ densities
+a run has reached it when every 100-cycle average of its e and O2+ densities
 stays within 5 % of it.  Small version of the benchmark experiment (9 training
 runs, 2 held-out points, 2000 cycles)."""
 import pytest

@@ -75,10 +75,11 @@ def test_settle_cycles_needs_every_later_average_inside_the_band():
     q = np.array([ref * v for v in levels])
     # the 5-window averages holding an early window or the excursion lie outside 5 %; from the
     # average of windows 9-13 on they all lie inside: cycle 130
-    assert W.settle_cycles(q, ref) == 130
-    assert W.settle_cycles(q[:12], ref) is None                               # ends on the excursion
-    assert W.settle_cycles(np.array([ref * 1.2] * 10), ref) is None          # never inside the band
-    assert W.settle_cycles(np.array([ref] * 10), ref) == 50                  # earliest: one full average
+    assert W.settle_cycles(q, ref, smooth=5) == 130
+    assert W.settle_cycles(q[:12], ref, smooth=5) is None                               # ends on the excursion
+    assert W.settle_cycles(np.array([ref * 1.2] * 10), ref, smooth=5) is None          # never inside the band
+    assert W.settle_cycles(np.array([ref] * 10), ref, smooth=5) == 50                  # earliest: one full average
+    assert W.settle_cycles(np.array([ref] * 12), ref) == 10 * W.SMOOTH              # the default window
 
 
 def test_r25_cycles_from_windows():
