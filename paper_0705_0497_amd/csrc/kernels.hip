@@ -210,28 +210,62 @@ __device__ T block_exclusive_scan(T v, T *buf, T &total) {
 // phi[ng] = 0.  Written as D[j+1/2] = D[1/2] + sum_{m=1..j} rho[m] dx (exact int64
 // prefix of the node charges), phi[j] = phi0 - (dx/eps0) sum_{m<j} D[m+1/2]; phi[ng] = 0
 // fixes D[1/2].  Same linear system as the tridiagonal one, solved by two scans.
-constexpr int FIELD_PER = 9;   // nodes per thread of the field block: (8192 + 1) / 1024 rounded up
+// nodes per thread of the field block, (N_g + 1) / 1024 rounded up to one of
+// these (the register arrays of a solve are sized by it; 8192 cells need 9)
+__host__ __device__ constexpr int field_nper(int nn) {
+  return nn <= 1024 ? 1 : nn <= 2048 ? 2 : nn <= 4096 ? 4 : nn <= 5120 ? 5 : 9;
+}
 
-// COHERENT: the node charges are read with device-coherent loads, for a caller
-// that runs in the same launch as the atomics that summed them.
-template <int BS, bool COHERENT = false>
+// What thread 0 of a field block reads for the current-density tally and the
+// step count, loaded at the start of the solve so that the round trips overlap
+// the charges' loads and the scans instead of following the solve one by one.
+struct TallyIn {
+  unsigned long long cnt[NSP], abs0[NSP], jcnt, nacc;
+  double e0_prev, u_prev, jsum, jpow0, jpow1;
+  int valid, ph;
+};
+
+__device__ __forceinline__ TallyIn tally_in(const Sim &S, int64_t step) {
+  const Scalars *sc = S.sc;
+  TallyIn ti;
+  ti.ph = step >= 1 ? (int)((step - 1) % S.spc) : 0;
+  ti.valid = sc->jvalid;
+  for (int s = 0; s < NSP; ++s) { ti.cnt[s] = sc->cnt[C_ABS0 + s]; ti.abs0[s] = sc->abs0_prev[s]; }
+  ti.e0_prev = sc->e0_prev;
+  ti.u_prev = sc->u_prev;
+  ti.jsum = S.jsum[ti.ph];
+  ti.jcnt = S.jcnt[ti.ph];
+  ti.jpow0 = S.jpow[0];
+  ti.jpow1 = S.jpow[1];
+  ti.nacc = S.nacc[0];
+  return ti;
+}
+
+// One block solves the field.  Wave w owns nodes [w 64 per, (w + 1) 64 per), its
+// lanes interleaved (round u, lane l: node w 64 per + 64 u + l), so that every
+// global load and store of the solve moves 64 consecutive nodes, and both
+// prefix sums are wave scans per round with a running carry plus one exchange
+// of the wave totals through LDS.  COHERENT: the node charges are read with
+// device-coherent loads, for a caller that runs in the same launch as the
+// atomics that summed them.  NPER >= ceil((N_g + 1) / BS).
+template <int BS, int NPER, bool COHERENT = false>
 __device__ void field_block(const Sim &S, int64_t step, int mode) {
-  static_assert(BS * FIELD_PER >= 8193, "the field block holds every node of the largest grid");
-  __shared__ long long sI[BS];
-  __shared__ double sJ[BS];
-  const int ng = S.ng, nn = ng + 1, t = threadIdx.x;
+  constexpr int NW = BS / 64;
+  __shared__ long long wI[NW];
+  __shared__ double wJ[NW];
+  const int ng = S.ng, nn = ng + 1, t = threadIdx.x, lane = t & 63, w = t >> 6;
   const int per = (nn + BS - 1) / BS;
-  const int j0 = min(t * per, nn), j1 = min(j0 + per, nn);
+  const int base = w * 64 * per + lane;            // node of round u: base + 64 u
   const bool ion = (step % S.ksub) == 0;
   const unsigned long long *Qe = S.Q, *Qp = S.Q + nn, *Qn = S.Q + 2 * nn;
   // this thread's node charges, read once: q_j = sum_s charge_s Q_s,j (fixed point)
-  unsigned long long qe[FIELD_PER], qp[FIELD_PER], qn[FIELD_PER];
-  long long q[FIELD_PER];
+  unsigned long long qe[NPER], qp[NPER], qn[NPER];
+  long long q[NPER];
 #pragma unroll
-  for (int u = 0; u < FIELD_PER; ++u) {
-    const int j = j0 + u;
+  for (int u = 0; u < NPER; ++u) {
+    const int j = base + 64 * u;
     qe[u] = qp[u] = qn[u] = 0ull;
-    if (j < j1) {
+    if (u < per && j < nn) {
       if (COHERENT) {
         qe[u] = __hip_atomic_load(Qe + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         qp[u] = __hip_atomic_load(Qp + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -244,105 +278,132 @@ __device__ void field_block(const Sim &S, int64_t step, int mode) {
            (long long)S.charge[2] * (long long)qn[u];
   }
   if (S.flags & F_EXT_FIELD) {
-    for (int j = j0; j < j1; ++j) {
-      S.E[j] = (float)(S.e_ext0 + S.e_ext1 * ((double)j * S.dx - 0.5 * S.L));
-      S.phi[j] = 0.0;
+#pragma unroll
+    for (int u = 0; u < NPER; ++u) {
+      const int j = base + 64 * u;
+      if (u < per && j < nn) {
+        S.E[j] = (float)(S.e_ext0 + S.e_ext1 * ((double)j * S.dx - 0.5 * S.L));
+        S.phi[j] = 0.0;
+      }
     }
   }
-  // the interior charges enter the first scan
-  long long loc = 0;
+  // cycle sums of the charge this solve sees, then clear what this step rebuilds
+  // (the solve works on q from here on)
+  if (mode == 0) {
 #pragma unroll
-  for (int u = 0; u < FIELD_PER; ++u) {
-    const int j = j0 + u;
-    if (j < j1 && j > 0 && j < ng) loc += q[u];
+    for (int u = 0; u < NPER; ++u) {
+      const int j = base + 64 * u;
+      if (u < per && j < nn) {
+        S.sumQ[j] += (double)qe[u];
+        S.sumQ[nn + j] += (double)qp[u];
+        S.sumQ[2 * nn + j] += (double)qn[u];
+        S.Q[j] = 0ull;
+        if (ion) { S.Q[nn + j] = 0ull; S.Q[2 * nn + j] = 0ull; }
+      }
+    }
   }
-  long long itot;
-  const long long ibase = block_exclusive_scan<BS, long long>(loc, sI, itot);
-  // second scan: J_j = sum_{m<j} I_m
-  double jloc = 0.0;
+  // the rf phase of this solve, and thread 0's tally inputs (kept in LDS)
+  __shared__ TallyIn sti;
+  const double u_now = S.U * sin(2.0 * M_PI * S.f * ((double)step * S.dt));
+  if (t == 0 && mode == 0) sti = tally_in(S, step);
+  // I_j = sum of the interior charges q_m, 1 <= m <= j (exact, int64)
+  long long icl[NPER];
   {
-    long long run = ibase;
+    long long carry = 0;
 #pragma unroll
-    for (int u = 0; u < FIELD_PER; ++u) {
-      const int j = j0 + u;
-      if (j >= j1) break;
-      if (j > 0 && j < ng) run += q[u];
-      if (j < ng) jloc += (double)run;
+    for (int u = 0; u < NPER; ++u) {
+      const int j = base + 64 * u;
+      icl[u] = wave_incl_scan((u < per && j > 0 && j < ng) ? q[u] : 0ll) + carry;
+      carry = __shfl(icl[u], 63, 64);
     }
+    if (lane == 63) wI[w] = carry;
   }
-  double jtot;
-  const double jbase = block_exclusive_scan<BS, double>(jloc, sJ, jtot);
-  double phiv[FIELD_PER];
+  __syncthreads();
+  long long ipre = 0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k)
+    if (k < w) ipre += wI[k];
+  // J_j = sum_{m < j} I_m (FP64), exclusive per node
+  double jex[NPER], jtot = 0.0;
+  {
+    double carry = 0.0;
+#pragma unroll
+    for (int u = 0; u < NPER; ++u) {
+      const int j = base + 64 * u;
+      const double jv = (u < per && j < ng) ? (double)(ipre + icl[u]) : 0.0;
+      const double x = wave_incl_scan(jv) + carry;
+      const double up = __shfl_up(x, 1, 64);
+      jex[u] = lane == 0 ? carry : up;
+      carry = __shfl(x, 63, 64);
+    }
+    if (lane == 63) wJ[w] = carry;
+  }
+  __syncthreads();
+  double jpre = 0.0;
+#pragma unroll
+  for (int k = 0; k < NW; ++k) {
+    const double x = wJ[k];
+    if (k < w) jpre += x;
+    jtot += x;
+  }
+  double phiv[NPER];
   double e0v = S.e_ext0 - 0.5 * S.e_ext1 * S.L;    // node-0 field (external-field mode)
+#pragma unroll
+  for (int u = 0; u < NPER; ++u) phiv[u] = 0.0;
   if (!(S.flags & F_EXT_FIELD)) {
     const double c = S.qcharge;            // e w 2^-32: charge per unit area per fixed-point unit
-    const double phi0 = S.U * sin(2.0 * M_PI * S.f * ((double)step * S.dt));
+    const double phi0 = u_now;
     const double d_half = (phi0 * S.eps0 / S.dx - c * jtot) / (double)ng;
     const double k = S.dx / S.eps0;
-    long long run = ibase;
-    double jrun = jbase;
 #pragma unroll
-    for (int u = 0; u < FIELD_PER; ++u) {
-      const int j = j0 + u;
-      phiv[u] = 0.0;
-      if (j >= j1) break;
-      const long long iprev = run;                 // I_{j-1}
-      if (j > 0 && j < ng) run += q[u];            // I_j
-      const double phi = (j == ng) ? 0.0 : phi0 - k * ((double)j * d_half + c * jrun);
+    for (int u = 0; u < NPER; ++u) {
+      const int j = base + 64 * u;
+      if (u >= per || j >= nn) continue;
+      const long long ij = ipre + icl[u];          // I_j
+      const long long iprev = ij - ((j > 0 && j < ng) ? q[u] : 0ll);   // I_{j-1}
+      const double phi = (j == ng) ? 0.0 : phi0 - k * ((double)j * d_half + c * (jpre + jex[u]));
       double e;
       if (j == 0) e = (d_half - c * (double)q[u]) / S.eps0;
       else if (j == ng) e = (d_half + c * (double)iprev + c * (double)q[u]) / S.eps0;
-      else e = (2.0 * d_half + c * ((double)iprev + (double)run)) / (2.0 * S.eps0);
+      else e = (2.0 * d_half + c * ((double)iprev + (double)ij)) / (2.0 * S.eps0);
       S.phi[j] = phi;
       S.E[j] = (float)e;
       phiv[u] = phi;
       if (j == 0) e0v = e;
-      if (j < ng) jrun += (double)run;
     }
-  } else {
-#pragma unroll
-    for (int u = 0; u < FIELD_PER; ++u) phiv[u] = 0.0;
   }
   // Section 3: current density at x = 0 in +x between this solve and the previous one,
   // eps0 dE_0/dt plus the charge absorbed at x = 0 in between, summed per rf phase
   if (t == 0) {
     Scalars *sc = S.sc;
-    const double u = S.U * sin(2.0 * M_PI * S.f * ((double)step * S.dt));
-    if (mode == 0 && sc->jvalid) {
+    const TallyIn ti = sti;
+    if (mode == 0 && ti.valid) {
       double dq = 0.0;
       for (int s = 0; s < NSP; ++s)
-        dq += (double)S.charge[s] * (double)(long long)(sc->cnt[C_ABS0 + s] - sc->abs0_prev[s]);
+        dq += (double)S.charge[s] * (double)(long long)(ti.cnt[s] - ti.abs0[s]);
       const double ew = S.qcharge * 4294967296.0;     // e w
-      const double jx = S.eps0 * (e0v - sc->e0_prev) / S.dt - ew * dq / S.dt;
-      const int ph = (int)((step - 1) % S.spc);
-      S.jsum[ph] += jx;
-      S.jcnt[ph] += 1ull;
-      S.jpow[0] += 0.5 * (sc->u_prev + u) * jx;
-      S.jpow[1] += 1.0;
+      const double jx = S.eps0 * (e0v - ti.e0_prev) / S.dt - ew * dq / S.dt;
+      S.jsum[ti.ph] = ti.jsum + jx;
+      S.jcnt[ti.ph] = ti.jcnt + 1ull;
+      S.jpow[0] = ti.jpow0 + 0.5 * (ti.u_prev + u_now) * jx;
+      S.jpow[1] = ti.jpow1 + 1.0;
     }
     if (mode == 0) {
       sc->e0_prev = e0v;
-      sc->u_prev = u;
-      for (int s = 0; s < NSP; ++s) sc->abs0_prev[s] = sc->cnt[C_ABS0 + s];
+      sc->u_prev = u_now;
+      for (int s = 0; s < NSP; ++s) sc->abs0_prev[s] = ti.cnt[s];
       sc->jvalid = 1;
     } else {
       sc->jvalid = 0;
     }
   }
   if (mode != 0) return;
-  // cycle sums of the state this solve saw, then clear what this step rebuilds
 #pragma unroll
-  for (int u = 0; u < FIELD_PER; ++u) {
-    const int j = j0 + u;
-    if (j >= j1) break;
-    S.sumQ[j] += (double)qe[u];
-    S.sumQ[nn + j] += (double)qp[u];
-    S.sumQ[2 * nn + j] += (double)qn[u];
-    S.sumphi[j] += phiv[u];
-    S.Q[j] = 0ull;
-    if (ion) { S.Q[nn + j] = 0ull; S.Q[2 * nn + j] = 0ull; }
+  for (int u = 0; u < NPER; ++u) {
+    const int j = base + 64 * u;
+    if (u < per && j < nn) S.sumphi[j] += phiv[u];
   }
-  if (t == 0) S.nacc[0] += 1ull;
+  if (t == 0) S.nacc[0] = sti.nacc + 1ull;
 }
 
 // ids of the previous step's products: per species, next_id + rank of the
@@ -409,10 +470,10 @@ __device__ void fixup_block(const Sim &S, int s, int *lds) {
   }
 }
 
-template <int BS>
+template <int BS, int NPER>
 __global__ __launch_bounds__(BS) void k_field(Sim S, int64_t step, int mode) {
   extern __shared__ int dyn_fix[];
-  if (blockIdx.x == 0) field_block<BS>(S, step, mode);
+  if (blockIdx.x == 0) field_block<BS, NPER>(S, step, mode);
   else fixup_block<BS>(S, blockIdx.x - 1, dyn_fix);
 }
 
@@ -423,7 +484,7 @@ __global__ __launch_bounds__(BS) void k_field(Sim S, int64_t step, int mode) {
 // b = r / nx, r / nx + RY, ... of node column r % nx.
 constexpr int RF_ROWS = 32;
 
-template <int BS>
+template <int BS, int NPER>
 __global__ __launch_bounds__(BS) void k_reduce_field(Sim S, int push_grid, int64_t next_step, int nred) {
   extern __shared__ int dyn_fix[];
   __shared__ int last;
@@ -451,7 +512,7 @@ __global__ __launch_bounds__(BS) void k_reduce_field(Sim S, int push_grid, int64
   __syncthreads();
   if (!last) return;
   if (threadIdx.x == 0) S.sc->field_ticket = 0u;
-  field_block<BS, true>(S, next_step, 0);
+  field_block<BS, NPER, true>(S, next_step, 0);
 }
 
 template <int BS>
@@ -2078,12 +2139,12 @@ __global__ __launch_bounds__(BS) void k_deposit(Sim S, int s) {
 // its step is base[m] + rel, and `mask` selects the members a launch works on.
 __device__ __forceinline__ bool in_mask(uint64_t mask, int m) { return (mask >> m) & 1ull; }
 
-template <int BS>
+template <int BS, int NPER>
 __global__ __launch_bounds__(BS) void k_field_b(const Sim *__restrict__ sims, const BatchDev *__restrict__ bd,
                                                  int rel) {
   extern __shared__ int dyn_fix[];
   const int m = blockIdx.y;
-  if (blockIdx.x == 0) field_block<BS>(sims[m], bd->base[m] + rel, 0);
+  if (blockIdx.x == 0) field_block<BS, NPER>(sims[m], bd->base[m] + rel, 0);
   else fixup_block<BS>(sims[m], blockIdx.x - 1, dyn_fix);
 }
 
@@ -2346,14 +2407,17 @@ hipError_t set_lds_limits(const Sim &S, int block) {
     else e = s == 0 ? SETA(1024, 0) : s == 1 ? SETA(1024, 1) : SETA(1024, 2);
 #undef SETA
   }
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_field<FBS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)fixup_lds_bytes(S));
+#define SET_FIELD_LDS(NP_)                                                                               \
+  if (e == hipSuccess)                                                                                   \
+    e = hipFuncSetAttribute((const void *)k_field<FBS, NP_>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                            (int)fixup_lds_bytes(S));                                                    \
+  if (e == hipSuccess)                                                                                   \
+    e = hipFuncSetAttribute((const void *)k_reduce_field<FBS, NP_>,                                      \
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)fixup_lds_bytes(S));
+  SET_FIELD_LDS(1) SET_FIELD_LDS(2) SET_FIELD_LDS(4) SET_FIELD_LDS(5) SET_FIELD_LDS(9)
+#undef SET_FIELD_LDS
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_fixup<FBS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)fixup_lds_bytes(S));
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_reduce_field<FBS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fixup_lds_bytes(S));
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void *)k_sort_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -2361,16 +2425,30 @@ hipError_t set_lds_limits(const Sim &S, int block) {
   return e;
 }
 
+#define FIELD_NPER_CASE(NP_, ...) \
+  case NP_: __VA_ARGS__; break;
+#define FIELD_NPER_SWITCH(nn_, LAUNCH_)                                                             \
+  switch (field_nper(nn_)) {                                                                        \
+    FIELD_NPER_CASE(1, LAUNCH_(1)) FIELD_NPER_CASE(2, LAUNCH_(2)) FIELD_NPER_CASE(4, LAUNCH_(4))     \
+    FIELD_NPER_CASE(5, LAUNCH_(5)) default: LAUNCH_(9);                                              \
+  }
+
 hipError_t launch_reduce_field(const Sim &S, int push_grid, int64_t next_step, hipStream_t st) {
   const int nred = ((S.ng + 1 + FBS - 1) / FBS) * RF_ROWS;
-  hipLaunchKernelGGL((k_reduce_field<FBS>), dim3(nred + NSP), dim3(FBS), fixup_lds_bytes(S), st, S, push_grid,
-                     next_step, nred);
+#define RF_LAUNCH(NP_)                                                                                   \
+  hipLaunchKernelGGL((k_reduce_field<FBS, NP_>), dim3(nred + NSP), dim3(FBS), fixup_lds_bytes(S), st, S, \
+                     push_grid, next_step, nred)
+  FIELD_NPER_SWITCH(S.ng + 1, RF_LAUNCH)
+#undef RF_LAUNCH
   return hipGetLastError();
 }
 
 hipError_t launch_field(const Sim &S, int64_t step, int mode, hipStream_t st) {
-  hipLaunchKernelGGL((k_field<FBS>), dim3(mode == 0 ? 1 + NSP : 1), dim3(FBS), fixup_lds_bytes(S), st, S, step,
-                     mode);
+#define F_LAUNCH(NP_)                                                                                     \
+  hipLaunchKernelGGL((k_field<FBS, NP_>), dim3(mode == 0 ? 1 + NSP : 1), dim3(FBS), fixup_lds_bytes(S), st, S, \
+                     step, mode)
+  FIELD_NPER_SWITCH(S.ng + 1, F_LAUNCH)
+#undef F_LAUNCH
   return hipGetLastError();
 }
 
@@ -2477,15 +2555,21 @@ hipError_t batch_push_occupancy(int block, int s, size_t lds, int *per_cu) {
   if (!fn) return hipErrorInvalidValue;
   hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void *)k_field_b<FBS>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)(2 * sizeof(int) * NBKT));
-  if (e != hipSuccess) return e;
+  for (const void *f : {(const void *)k_field_b<FBS, 1>, (const void *)k_field_b<FBS, 2>,
+                        (const void *)k_field_b<FBS, 4>, (const void *)k_field_b<FBS, 5>,
+                        (const void *)k_field_b<FBS, 9>}) {
+    e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)(2 * sizeof(int) * NBKT));
+    if (e != hipSuccess) return e;
+  }
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, block, lds);
 }
 
 hipError_t launch_field_b(const BatchLaunch &B, int rel, hipStream_t st) {
-  hipLaunchKernelGGL((k_field_b<FBS>), dim3(1 + NSP, B.nmem), dim3(FBS), 2 * sizeof(int) * NBKT, st, B.sims, B.bd,
-                     rel);
+#define FB_LAUNCH(NP_)                                                                                     \
+  hipLaunchKernelGGL((k_field_b<FBS, NP_>), dim3(1 + NSP, B.nmem), dim3(FBS), 2 * sizeof(int) * NBKT, st, B.sims, \
+                     B.bd, rel)
+  FIELD_NPER_SWITCH(B.nn_max, FB_LAUNCH)
+#undef FB_LAUNCH
   return hipGetLastError();
 }
 
