@@ -185,6 +185,45 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
   return v;
 }
 
+// Inclusive wave scan on DPP row shifts and row broadcasts (lanes within a row
+// of 16 by 1, 2, 4, 8, then row 0's and rows 0-1's totals into the rows
+// above): no LDS round trip per step, unlike the shuffle form above.  64-bit
+// values move as two 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ long long dpp_move(long long x) {
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)x, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(x >> 32), CTRL, 0xf, 0xf, false);
+  return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x) {
+  return __builtin_bit_cast(double, dpp_move<CTRL>(__builtin_bit_cast(long long, x)));
+}
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan_dpp(T v) {
+  const int lane = threadIdx.x & 63, rl = lane & 15;
+  T x = dpp_move<0x111>(v);
+  if (rl >= 1) v += x;
+  x = dpp_move<0x112>(v);
+  if (rl >= 2) v += x;
+  x = dpp_move<0x114>(v);
+  if (rl >= 4) v += x;
+  x = dpp_move<0x118>(v);
+  if (rl >= 8) v += x;
+  x = dpp_move<0x142>(v);                          // row_bcast:15
+  if ((lane & 31) >= 16) v += x;
+  x = dpp_move<0x143>(v);                          // row_bcast:31
+  if (lane >= 32) v += x;
+  return v;
+}
+__device__ __forceinline__ long long wave_lane63(long long x) {
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)x, 63), hi = __builtin_amdgcn_readlane((int)(x >> 32), 63);
+  return (long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned long long)(unsigned)lo);
+}
+__device__ __forceinline__ double wave_lane63(double x) {
+  return __builtin_bit_cast(double, wave_lane63(__builtin_bit_cast(long long, x)));
+}
+
 // exclusive scan over the block (BS a multiple of 64); buf holds BS/64 entries
 template <int BS, typename T>
 __device__ T block_exclusive_scan(T v, T *buf, T &total) {
@@ -258,13 +297,17 @@ __device__ void field_block(const Sim &S, int64_t step, int mode) {
   const int base = w * 64 * per + lane;            // node of round u: base + 64 u
   const bool ion = (step % S.ksub) == 0;
   const unsigned long long *Qe = S.Q, *Qp = S.Q + nn, *Qn = S.Q + 2 * nn;
-  // this thread's node charges, read once: q_j = sum_s charge_s Q_s,j (fixed point)
+  // every load of the solve is issued here, before any store, so that they are
+  // in flight together: this thread's node charges, the cycle sums they and the
+  // potential are added to, and thread 0's tally inputs
   unsigned long long qe[NPER], qp[NPER], qn[NPER];
+  double sq0[NPER], sq1[NPER], sq2[NPER], sph[NPER];
   long long q[NPER];
 #pragma unroll
   for (int u = 0; u < NPER; ++u) {
     const int j = base + 64 * u;
     qe[u] = qp[u] = qn[u] = 0ull;
+    sq0[u] = sq1[u] = sq2[u] = sph[u] = 0.0;
     if (u < per && j < nn) {
       if (COHERENT) {
         qe[u] = __hip_atomic_load(Qe + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -273,10 +316,17 @@ __device__ void field_block(const Sim &S, int64_t step, int mode) {
       } else {
         qe[u] = Qe[j]; qp[u] = Qp[j]; qn[u] = Qn[j];
       }
+      if (mode == 0) { sq0[u] = S.sumQ[j]; sq1[u] = S.sumQ[nn + j]; sq2[u] = S.sumQ[2 * nn + j]; sph[u] = S.sumphi[j]; }
     }
+  }
+  // the rf phase of this solve, computed while the loads are in flight
+  const double u_now = S.U * sin(2.0 * M_PI * S.f * ((double)step * S.dt));
+  __shared__ TallyIn sti;
+  if (t == 0 && mode == 0) sti = tally_in(S, step);
+#pragma unroll
+  for (int u = 0; u < NPER; ++u)
     q[u] = (long long)S.charge[0] * (long long)qe[u] + (long long)S.charge[1] * (long long)qp[u] +
            (long long)S.charge[2] * (long long)qn[u];
-  }
   if (S.flags & F_EXT_FIELD) {
 #pragma unroll
     for (int u = 0; u < NPER; ++u) {
@@ -294,18 +344,14 @@ __device__ void field_block(const Sim &S, int64_t step, int mode) {
     for (int u = 0; u < NPER; ++u) {
       const int j = base + 64 * u;
       if (u < per && j < nn) {
-        S.sumQ[j] += (double)qe[u];
-        S.sumQ[nn + j] += (double)qp[u];
-        S.sumQ[2 * nn + j] += (double)qn[u];
+        S.sumQ[j] = sq0[u] + (double)qe[u];
+        S.sumQ[nn + j] = sq1[u] + (double)qp[u];
+        S.sumQ[2 * nn + j] = sq2[u] + (double)qn[u];
         S.Q[j] = 0ull;
         if (ion) { S.Q[nn + j] = 0ull; S.Q[2 * nn + j] = 0ull; }
       }
     }
   }
-  // the rf phase of this solve, and thread 0's tally inputs (kept in LDS)
-  __shared__ TallyIn sti;
-  const double u_now = S.U * sin(2.0 * M_PI * S.f * ((double)step * S.dt));
-  if (t == 0 && mode == 0) sti = tally_in(S, step);
   // I_j = sum of the interior charges q_m, 1 <= m <= j (exact, int64)
   long long icl[NPER];
   {
@@ -313,8 +359,8 @@ __device__ void field_block(const Sim &S, int64_t step, int mode) {
 #pragma unroll
     for (int u = 0; u < NPER; ++u) {
       const int j = base + 64 * u;
-      icl[u] = wave_incl_scan((u < per && j > 0 && j < ng) ? q[u] : 0ll) + carry;
-      carry = __shfl(icl[u], 63, 64);
+      icl[u] = wave_incl_scan_dpp((u < per && j > 0 && j < ng) ? q[u] : 0ll) + carry;
+      carry = wave_lane63(icl[u]);
     }
     if (lane == 63) wI[w] = carry;
   }
@@ -331,10 +377,10 @@ __device__ void field_block(const Sim &S, int64_t step, int mode) {
     for (int u = 0; u < NPER; ++u) {
       const int j = base + 64 * u;
       const double jv = (u < per && j < ng) ? (double)(ipre + icl[u]) : 0.0;
-      const double x = wave_incl_scan(jv) + carry;
+      const double x = wave_incl_scan_dpp(jv) + carry;
       const double up = __shfl_up(x, 1, 64);
       jex[u] = lane == 0 ? carry : up;
-      carry = __shfl(x, 63, 64);
+      carry = wave_lane63(x);
     }
     if (lane == 63) wJ[w] = carry;
   }
@@ -401,7 +447,7 @@ __device__ void field_block(const Sim &S, int64_t step, int mode) {
 #pragma unroll
   for (int u = 0; u < NPER; ++u) {
     const int j = base + 64 * u;
-    if (u < per && j < nn) S.sumphi[j] += phiv[u];
+    if (u < per && j < nn) S.sumphi[j] = sph[u] + phiv[u];
   }
   if (t == 0) S.nacc[0] = sti.nacc + 1ull;
 }
