@@ -569,10 +569,10 @@ __global__ __launch_bounds__(BS) void k_fixup(Sim S) {
 
 // ---------------------------------------------------------------- particle step
 // A block owns a contiguous chunk of the store (a multiple of GROUP slots).  Per
-// pass each thread takes GROUP consecutive particles with 128-bit loads and
-// stores, keeps consecutive deposits into one cell in registers, and queues the
-// slots of collision candidates in LDS; after the pass the whole block works the
-// queue with all lanes.  The block's charge histogram stays in LDS and is written
+// pass each thread takes GROUP (ions) or ESLOTS (electrons) consecutive particles
+// with 128-bit loads and stores, keeps consecutive deposits into one cell in
+// registers, and queues the slots of collision candidates in LDS; after the pass
+// the block (ions) or the wave (electrons) works the queue with all its lanes.  The block's charge histogram stays in LDS and is written
 // out as one partial per block; k_reduce adds the partials into the species
 // histogram, so no global atomics are needed for the bulk of the charge.
 constexpr int GROUP = 8;
@@ -585,7 +585,10 @@ constexpr int CAND_ILP = PICMCC_CAND_ILP;   // candidates whose gathers a thread
 #endif
 // electron slots per lane whose free-flight ends a wave lists before working them
 constexpr int FFE_SLOTS = PICMCC_FFE_SLOTS;
-static_assert(GROUP % FFE_SLOTS == 0, "FFE_SLOTS divides GROUP");
+// electron slots per lane in one pass (a pass's fields and the next pass's are live
+// together, so the pass is half as wide as the ion one)
+constexpr int ESLOTS = 4;
+static_assert(GROUP % ESLOTS == 0 && ESLOTS % FFE_SLOTS == 0, "FFE_SLOTS divides ESLOTS divides GROUP");
 // outcome flags of a listed free-flight end, in the (zero) cell bits of its new flight
 constexpr uint32_t FFE_CAND = 1u, FFE_REDRAW = 2u;
 
@@ -942,7 +945,7 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
   const int lane = threadIdx.x & 63;
   // Electrons: each wave lists the free-flight ends of FFE_SLOTS slots per lane and
   // works the list on full lanes (draw, next flight, rate bound), then queues the
-  // collision candidates of its own GROUP * 64 slots of a pass (their state as LDS
+  // collision candidates of its own ESLOTS * 64 slots of a pass (their state as LDS
   // records while the wave's share lasts) and works them off itself, so the waves
   // of a block never wait for each other inside a run.  Ions: one queue per block,
   // worked off by all its lanes between two barriers.
@@ -955,35 +958,52 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
     const unsigned long long below = (1ull << lane) - 1ull;
     uint32_t *fid = sh.fid + wv * FFE_SLOTS * 64;
     float *fv2 = sh.fv2 + wv * FFE_SLOTS * 64;
-    // one wave's pass over the 512 slots from ub (wave-uniform)
-    auto pass = [&](const int64_t ub) __attribute__((always_inline)) {
-      const int64_t i0 = ub + (int64_t)GROUP * lane;
-      const int nv = i0 < end ? (int)min((int64_t)GROUP, end - i0) : 0;
-      int32_t w[GROUP];
-      float off[GROUP], vx[GROUP], vy[GROUP], vz[GROUP];
-      uint32_t id[GROUP];
+    // A lane works ESLOTS consecutive slots per pass, and the fields of its next
+    // pass are loaded before the work of this one (the pushes, the free-flight ends
+    // and the wave's candidate queue all run under those loads).  Every cache line
+    // of the cold fields is needed anyway (a third of the electrons end a free
+    // flight each step), so they stream in with the hot ones.
+    struct ESlots {
+      int32_t w[ESLOTS];
+      float off[ESLOTS], vx[ESLOTS], vy[ESLOTS], vz[ESLOTS];
+      uint32_t id[ESLOTS];
+    };
+    auto load_slots = [&](const int64_t ub, ESlots &d) __attribute__((always_inline)) {
+      const int64_t i0 = ub + (int64_t)ESLOTS * lane;
+      const int nv = i0 < end ? (int)min((int64_t)ESLOTS, end - i0) : 0;
       if (nv > 0) {
-        // every cache line of the cold fields is needed anyway (a third of the
-        // electrons end a free flight each step), so they stream in with the hot ones
-        const int4 wa = *reinterpret_cast<const int4 *>(P.w + i0), wb = *reinterpret_cast<const int4 *>(P.w + i0 + 4);
-        const float4 oa = *reinterpret_cast<const float4 *>(P.off + i0), ob = *reinterpret_cast<const float4 *>(P.off + i0 + 4);
-        const float4 va = *reinterpret_cast<const float4 *>(P.vx + i0), vb = *reinterpret_cast<const float4 *>(P.vx + i0 + 4);
-        const uint4 ia = *reinterpret_cast<const uint4 *>(P.id + i0), ib = *reinterpret_cast<const uint4 *>(P.id + i0 + 4);
-        const float4 ya = *reinterpret_cast<const float4 *>(P.vy + i0), yb = *reinterpret_cast<const float4 *>(P.vy + i0 + 4);
-        const float4 za = *reinterpret_cast<const float4 *>(P.vz + i0), zb = *reinterpret_cast<const float4 *>(P.vz + i0 + 4);
-        w[0] = wa.x; w[1] = wa.y; w[2] = wa.z; w[3] = wa.w; w[4] = wb.x; w[5] = wb.y; w[6] = wb.z; w[7] = wb.w;
-        off[0] = oa.x; off[1] = oa.y; off[2] = oa.z; off[3] = oa.w; off[4] = ob.x; off[5] = ob.y; off[6] = ob.z; off[7] = ob.w;
-        vx[0] = va.x; vx[1] = va.y; vx[2] = va.z; vx[3] = va.w; vx[4] = vb.x; vx[5] = vb.y; vx[6] = vb.z; vx[7] = vb.w;
-        id[0] = ia.x; id[1] = ia.y; id[2] = ia.z; id[3] = ia.w; id[4] = ib.x; id[5] = ib.y; id[6] = ib.z; id[7] = ib.w;
-        vy[0] = ya.x; vy[1] = ya.y; vy[2] = ya.z; vy[3] = ya.w; vy[4] = yb.x; vy[5] = yb.y; vy[6] = yb.z; vy[7] = yb.w;
-        vz[0] = za.x; vz[1] = za.y; vz[2] = za.z; vz[3] = za.w; vz[4] = zb.x; vz[5] = zb.y; vz[6] = zb.z; vz[7] = zb.w;
+        const int4 wa = *reinterpret_cast<const int4 *>(P.w + i0);
+        const float4 oa = *reinterpret_cast<const float4 *>(P.off + i0), va = *reinterpret_cast<const float4 *>(P.vx + i0);
+        const uint4 ia = *reinterpret_cast<const uint4 *>(P.id + i0);
+        const float4 ya = *reinterpret_cast<const float4 *>(P.vy + i0), za = *reinterpret_cast<const float4 *>(P.vz + i0);
+        d.w[0] = wa.x; d.w[1] = wa.y; d.w[2] = wa.z; d.w[3] = wa.w;
+        d.off[0] = oa.x; d.off[1] = oa.y; d.off[2] = oa.z; d.off[3] = oa.w;
+        d.vx[0] = va.x; d.vx[1] = va.y; d.vx[2] = va.z; d.vx[3] = va.w;
+        d.id[0] = ia.x; d.id[1] = ia.y; d.id[2] = ia.z; d.id[3] = ia.w;
+        d.vy[0] = ya.x; d.vy[1] = ya.y; d.vy[2] = ya.z; d.vy[3] = ya.w;
+        d.vz[0] = za.x; d.vz[1] = za.y; d.vz[2] = za.z; d.vz[3] = za.w;
+#pragma unroll
+        for (int k = 0; k < ESLOTS; ++k)          // slots past the block's range are not its own
+          if (k >= nv) d.w[k] = W_DEAD;
       } else {
 #pragma unroll
-        for (int k = 0; k < GROUP; ++k) { w[k] = W_DEAD; off[k] = vx[k] = vy[k] = vz[k] = 0.0f; id[k] = 0u; }
+        for (int k = 0; k < ESLOTS; ++k) { d.w[k] = W_DEAD; d.off[k] = d.vx[k] = d.vy[k] = d.vz[k] = 0.0f; d.id[k] = 0u; }
+      }
+    };
+    // one wave's pass over the ESLOTS * 64 slots from ub (wave-uniform)
+    auto pass = [&](const int64_t ub, const ESlots &d) __attribute__((always_inline)) {
+      const int64_t i0 = ub + (int64_t)ESLOTS * lane;
+      const int nv = i0 < end ? (int)min((int64_t)ESLOTS, end - i0) : 0;
+      int32_t w[ESLOTS];
+      float off[ESLOTS], vx[ESLOTS], vy[ESLOTS], vz[ESLOTS];
+      uint32_t id[ESLOTS];
+#pragma unroll
+      for (int k = 0; k < ESLOTS; ++k) {
+        w[k] = d.w[k]; off[k] = d.off[k]; vx[k] = d.vx[k]; vy[k] = d.vy[k]; vz[k] = d.vz[k]; id[k] = d.id[k];
       }
       int nq = 0;                                  // candidates this wave queued in this pass
 #pragma unroll
-      for (int k0 = 0; k0 < GROUP; k0 += FFE_SLOTS) {
+      for (int k0 = 0; k0 < ESLOTS; k0 += FFE_SLOTS) {
         // push FFE_SLOTS slots; list the ones whose free flight ends
         unsigned int ended = 0u;
         int nf = 0;
@@ -1104,13 +1124,10 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
       }
-      if (nv == GROUP) {
+      if (nv == ESLOTS) {
         *reinterpret_cast<int4 *>(P.w + i0) = make_int4(w[0], w[1], w[2], w[3]);
-        *reinterpret_cast<int4 *>(P.w + i0 + 4) = make_int4(w[4], w[5], w[6], w[7]);
         *reinterpret_cast<float4 *>(P.off + i0) = make_float4(off[0], off[1], off[2], off[3]);
-        *reinterpret_cast<float4 *>(P.off + i0 + 4) = make_float4(off[4], off[5], off[6], off[7]);
         *reinterpret_cast<float4 *>(P.vx + i0) = make_float4(vx[0], vx[1], vx[2], vx[3]);
-        *reinterpret_cast<float4 *>(P.vx + i0 + 4) = make_float4(vx[4], vx[5], vx[6], vx[7]);
       } else {
         for (int k = 0; k < nv; ++k) { P.w[i0 + k] = w[k]; P.off[i0 + k] = off[k]; P.vx[i0 + k] = vx[k]; }
       }
@@ -1134,8 +1151,16 @@ __device__ __forceinline__ void push_run(const Sim &S, int64_t step, int64_t beg
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     };
-    for (int64_t base = begin; base < end; base += (int64_t)GROUP * BS)
-      if (base + (int64_t)wv * GROUP * 64 < end) pass(base + (int64_t)wv * GROUP * 64);
+    // the passes of one wave: ub advances by the block's ESLOTS * BS slots
+    const int64_t stride = (int64_t)ESLOTS * BS;
+    int64_t ub = begin + (int64_t)wv * ESLOTS * 64;
+    ESlots cur, nxt;
+    if (ub < end) load_slots(ub, cur);
+    for (; ub < end; ub += stride) {
+      if (ub + stride < end) load_slots(ub + stride, nxt);
+      pass(ub, cur);
+      cur = nxt;
+    }
   } else {
   int par = 0;
   for (int64_t base = begin; base < end; base += (int64_t)GROUP * BS, par ^= 1) {
