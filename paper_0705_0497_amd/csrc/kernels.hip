@@ -2097,15 +2097,37 @@ __device__ void diag_block(const Sim &S, int s, unsigned char *dsm) {
   __syncthreads();
   const Particles &P = S.p[s];
   const int64_t N = (int64_t)S.sc->n[s];
-  for (int64_t i = (int64_t)blockIdx.x * BS + threadIdx.x; i < N; i += (int64_t)gridDim.x * BS) {
-    const int32_t w = P.w[i];
-    if (w < 0) continue;
-    const float vx = P.vx[i], vy = P.vy[i], vz = P.vz[i];
-    const float e = S.half_m_e[s] * (vx * vx + vy * vy + vz * vz);
-    const int c = w & (int32_t)W_CELL;
-    atomicAdd(&le[c], (unsigned long long)__float2ll_rn(e * 1048576.0f));
-    atomicAdd(&lc[c], 1u);
-    atomicAdd(&lb[ebin(e)], 1u);
+  // four consecutive particles per thread and pass, with 128-bit loads (the store's
+  // fields are 16-byte aligned); a ragged tail is read element by element
+  for (int64_t i0 = 4 * ((int64_t)blockIdx.x * BS + threadIdx.x); i0 < N; i0 += 4 * (int64_t)gridDim.x * BS) {
+    int32_t w[4];
+    float vx[4], vy[4], vz[4];
+    if (i0 + 4 <= N) {
+      const int4 wa = *reinterpret_cast<const int4 *>(P.w + i0);
+      const float4 xa = *reinterpret_cast<const float4 *>(P.vx + i0);
+      const float4 ya = *reinterpret_cast<const float4 *>(P.vy + i0);
+      const float4 za = *reinterpret_cast<const float4 *>(P.vz + i0);
+      w[0] = wa.x; w[1] = wa.y; w[2] = wa.z; w[3] = wa.w;
+      vx[0] = xa.x; vx[1] = xa.y; vx[2] = xa.z; vx[3] = xa.w;
+      vy[0] = ya.x; vy[1] = ya.y; vy[2] = ya.z; vy[3] = ya.w;
+      vz[0] = za.x; vz[1] = za.y; vz[2] = za.z; vz[3] = za.w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        w[k] = -1;
+        vx[k] = vy[k] = vz[k] = 0.0f;
+        if (i0 + k < N) { w[k] = P.w[i0 + k]; vx[k] = P.vx[i0 + k]; vy[k] = P.vy[i0 + k]; vz[k] = P.vz[i0 + k]; }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (w[k] < 0) continue;
+      const float e = S.half_m_e[s] * (vx[k] * vx[k] + vy[k] * vy[k] + vz[k] * vz[k]);
+      const int c = w[k] & (int32_t)W_CELL;
+      atomicAdd(&le[c], (unsigned long long)__float2ll_rn(e * 1048576.0f));
+      atomicAdd(&lc[c], 1u);
+      atomicAdd(&lb[ebin(e)], 1u);
+    }
   }
   __syncthreads();
   for (int j = threadIdx.x; j < ng; j += BS) {
