@@ -1460,6 +1460,21 @@ __device__ __forceinline__ void pair_count_kills(const Sim &S, int sp, bool kill
     atomicAdd(&S.sc->cnt[sp == 1 ? C_PAIRED : C_PAIRED_NEG], (unsigned long long)__popcll(m));
 }
 
+// cell words of the four slots from i0 (a multiple of 4; the store's fields are
+// 16-byte aligned): one 128-bit load, slots at or beyond n read as dead
+__device__ __forceinline__ void load_w4(const int32_t *wp, int64_t i0, int64_t n, int32_t w[4]) {
+  if (i0 + 4 <= n) {
+    const int4 a = *reinterpret_cast<const int4 *>(wp + i0);
+    w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+  } else {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      w[k] = W_DEAD;
+      if (i0 + k < n) w[k] = wp[i0 + k];
+    }
+  }
+}
+
 template <int BS>
 __device__ void pair_hist(const Sim &S, int64_t step, int sp, int bx, int gx) {
   if (!*pair_active_flag(S, sp)) return;
@@ -1467,13 +1482,17 @@ __device__ void pair_hist(const Sim &S, int64_t step, int sp, int bx, int gx) {
   const int32_t *kl = sp == 1 ? S.kleft : S.kleft_neg;
   const Particles &P = S.p[sp];
   const int64_t N = (int64_t)S.sc->n[sp];
-  for (int64_t i = (int64_t)bx * BS + threadIdx.x; i < N; i += (int64_t)gx * BS) {
-    const int32_t w = P.w[i];
-    if (w < 0) continue;
-    const int c = w & (int32_t)W_CELL;
-    if (kl[c] <= 0) continue;
-    const uint32_t x = pair_draw(S, sp, P.id[i], step);
-    atomicAdd(&S.phist[(size_t)c * PAIR_NB + (x >> 24)], 1);
+  for (int64_t i0 = 4 * ((int64_t)bx * BS + threadIdx.x); i0 < N; i0 += 4 * (int64_t)gx * BS) {
+    int32_t w[4];
+    load_w4(P.w, i0, N, w);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      if (w[k] < 0) continue;
+      const int c = w[k] & (int32_t)W_CELL;
+      if (kl[c] <= 0) continue;
+      const uint32_t x = pair_draw(S, sp, P.id[i0 + k], step);
+      atomicAdd(&S.phist[(size_t)c * PAIR_NB + (x >> 24)], 1);
+    }
   }
 }
 
@@ -1532,31 +1551,37 @@ __device__ void pair_take(const Sim &S, int64_t step, int sp, int bx, int gx) {
   const Particles &P = S.p[sp];
   const Particles &L = S.alt[sp];
   const int64_t N = (int64_t)S.sc->n[sp];
-  // whole waves step through the slots so that the kill counts are wave-aggregated
-  const int64_t n_pad = (N + 63) & ~(int64_t)63;
-  for (int64_t i = (int64_t)bx * BS + threadIdx.x; i < n_pad; i += (int64_t)gx * BS) {
-    bool killed = false;
-    const int32_t w = i < N ? P.w[i] : W_DEAD;
-    if (w >= 0) {
-      const int c = w & (int32_t)W_CELL;
-      const PairCell rec = S.pcell[c];
-      if (rec.bstar > 0 || rec.need > 0) {
-        const uint32_t id = P.id[i];
-        const uint32_t x = pair_draw(S, sp, id, step);
-        const int b = (int)(x >> 24);
-        if (b < rec.bstar) {
-          pair_kill(S, sp, i, c, P.off[i]);
-          killed = true;
-        } else if (b == rec.bstar && rec.need > 0) {
-          const int e = rec.segoff + atomicAdd(&S.pcell[c].fill, 1);
-          reinterpret_cast<uint32_t *>(L.vx)[e] = x;
-          L.id[e] = id;
-          L.w[e] = (int32_t)i;
-          reinterpret_cast<int32_t *>(L.vy)[e] = c;
+  // whole waves step through the slots (a wave takes 256 consecutive ones) so that
+  // the kill counts are wave-aggregated
+  const int64_t n_pad = (N + 255) & ~(int64_t)255;
+  for (int64_t i0 = 4 * ((int64_t)bx * BS + threadIdx.x); i0 < n_pad; i0 += 4 * (int64_t)gx * BS) {
+    int32_t w[4];
+    load_w4(P.w, i0, N, w);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int64_t i = i0 + k;
+      bool killed = false;
+      if (w[k] >= 0) {
+        const int c = w[k] & (int32_t)W_CELL;
+        const PairCell rec = S.pcell[c];
+        if (rec.bstar > 0 || rec.need > 0) {
+          const uint32_t id = P.id[i];
+          const uint32_t x = pair_draw(S, sp, id, step);
+          const int b = (int)(x >> 24);
+          if (b < rec.bstar) {
+            pair_kill(S, sp, i, c, P.off[i]);
+            killed = true;
+          } else if (b == rec.bstar && rec.need > 0) {
+            const int e = rec.segoff + atomicAdd(&S.pcell[c].fill, 1);
+            reinterpret_cast<uint32_t *>(L.vx)[e] = x;
+            L.id[e] = id;
+            L.w[e] = (int32_t)i;
+            reinterpret_cast<int32_t *>(L.vy)[e] = c;
+          }
         }
       }
+      pair_count_kills(S, sp, killed);
     }
-    pair_count_kills(S, sp, killed);
   }
 }
 
