@@ -82,6 +82,27 @@ def test_energy_moments_single_step(step0):
     assert np.max(np.abs(mg["sum_phi"] - mo["sumphi"])) <= 1e-12 * np.max(np.abs(mo["sumphi"]))
 
 
+def test_energy_moments_of_ragged_stores():
+    """Stores whose sizes leave 1, 2 and 3 slots after the last full group of the
+    four slots a thread reads at once: every particle is sampled once."""
+    d = I.config(1, diag_every=1)
+    procs = I.make_processes()
+    st, nid, step = H.canonical_from_oracle(d, procs, seed_steps=30)
+    trimmed = []
+    for s in range(3):
+        n = len(st[s]["id"])
+        keep = n - (n - (s + 1)) % 4
+        trimmed.append({k: v[:keep] for k, v in st[s].items()})
+    assert [len(t["id"]) % 4 for t in trimmed] == [1, 2, 3]
+    o = H.oracle_from_canonical(d, procs, trimmed, nid, step)
+    g = H.gpu_from_canonical(d, procs, trimmed, nid, step)
+    o.reset_moments()
+    g.moments(reset=True)
+    o.step(1)
+    g.step(1)
+    _check_sample(g.moments(), o.moments(), trimmed, d.species())
+
+
 def _state_moments_after(cfg, steps, **kw):
     """The GPU runs `steps` steps, then records one diagnostic sample of its state;
     the oracle samples the same state."""
