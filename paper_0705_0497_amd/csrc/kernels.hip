@@ -1896,30 +1896,45 @@ __global__ __launch_bounds__(BS) void k_sort_scan(Sim S, int s) {
   }
 }
 
-// Scatter into the other buffer, a tile of SORT_T particles at a time (all six
-// fields loaded with 64-bit reads).  When the live cells of a tile span at most
-// SORT_NB cells (the usual case: between two sorts an ion crosses a few cells,
+// Scatter into the other buffer, a tile of SORT_BS * G particles at a time (all six
+// fields loaded with 64- or 128-bit reads; the larger the tile, the more of each
+// cell's particles one tile writes together, so fewer partially written lines are
+// written back).  When the live cells of a tile span at most SORT_NB cells (the usual case: between two sorts an ion crosses a few cells,
 // an electron some tens), the tile is ordered by cell in LDS and written out
 // with consecutive lanes on consecutive slots of the block's cell ranges.  A
 // wider tile (products appended since the last sort) writes each particle
 // where it goes.  Within a cell the order is that of the LDS reservations.
-constexpr int SORT_BS = 1024, SORT_G = 2, SORT_T = SORT_BS * SORT_G, SORT_NB = 1024;
+constexpr int SORT_BS = 1024, SORT_NB = 1024;
+// LDS of one workgroup on gfx950
+constexpr size_t SORT_LDS_MAX = 160 * 1024;
 
+template <int G>   // particles per thread and tile
 struct SortTile {
-  int32_t w[SORT_T];
-  float off[SORT_T], vx[SORT_T], vy[SORT_T], vz[SORT_T];
-  uint32_t id[SORT_T];
+  static constexpr int T = SORT_BS * G;
+  int32_t w[T];
+  float off[T], vx[T], vy[T], vz[T];
+  uint32_t id[T];
   int32_t cnt[SORT_NB], start[SORT_NB], base[SORT_NB];
   int32_t lo[SORT_BS / 64], hi[SORT_BS / 64], scan[SORT_BS / 64];
 };
 
-size_t sort_lds_bytes(const Sim &S) { return sizeof(SortTile) + 2 * sizeof(int32_t) * (size_t)S.ng; }
+template <int G>
+size_t sort_lds_bytes_g(const Sim &S) { return sizeof(SortTile<G>) + 2 * sizeof(int32_t) * (size_t)S.ng; }
 
+// tiles of 4096 where the block's LDS holds one beside the block's cell ranges
+// (up to 6632 cells), else of 2048
+int sort_tile_g(const Sim &S) { return sort_lds_bytes_g<4>(S) <= SORT_LDS_MAX ? 4 : 2; }
+
+size_t sort_lds_bytes(const Sim &S) { return sort_tile_g(S) == 4 ? sort_lds_bytes_g<4>(S) : sort_lds_bytes_g<2>(S); }
+
+template <int G>
 __global__ __launch_bounds__(SORT_BS) void k_sort_scatter(Sim S, int s, Particles dst) {
+  static_assert(G == 2 || G == 4, "tiles of two or four particles per thread");
+  constexpr int T = SortTile<G>::T;
   extern __shared__ __align__(16) unsigned char sort_lds[];
-  SortTile &t = *reinterpret_cast<SortTile *>(sort_lds);
+  SortTile<G> &t = *reinterpret_cast<SortTile<G> *>(sort_lds);
   const int ng = S.ng;
-  int32_t *lbase = reinterpret_cast<int32_t *>(sort_lds + sizeof(SortTile)), *lfill = lbase + ng;
+  int32_t *lbase = reinterpret_cast<int32_t *>(sort_lds + sizeof(SortTile<G>)), *lfill = lbase + ng;
   const int64_t N = (int64_t)S.sc->nsort[s];
   const int64_t chunk = push_chunk(N, gridDim.x);
   const int64_t begin = (int64_t)blockIdx.x * chunk, end = min(N, begin + chunk);
@@ -1931,24 +1946,44 @@ __global__ __launch_bounds__(SORT_BS) void k_sort_scatter(Sim S, int s, Particle
   }
   const Particles &P = S.p[s];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int64_t tb = begin; tb < end; tb += SORT_T) {
-    const int64_t i0 = tb + (int64_t)SORT_G * threadIdx.x;
-    int32_t w[SORT_G] = {W_DEAD, W_DEAD};
-    float off[SORT_G], vx[SORT_G], vy[SORT_G], vz[SORT_G];
-    uint32_t id[SORT_G];
+  for (int64_t tb = begin; tb < end; tb += T) {
+    const int64_t i0 = tb + (int64_t)G * threadIdx.x;
+    int32_t w[G];
+    float off[G], vx[G], vy[G], vz[G];
+    uint32_t id[G];
+#pragma unroll
+    for (int k = 0; k < G; ++k) w[k] = W_DEAD;
     if (i0 < end) {
-      const int2 a = *reinterpret_cast<const int2 *>(P.w + i0);
-      const float2 o = *reinterpret_cast<const float2 *>(P.off + i0), x = *reinterpret_cast<const float2 *>(P.vx + i0),
-                   y = *reinterpret_cast<const float2 *>(P.vy + i0), z = *reinterpret_cast<const float2 *>(P.vz + i0);
-      const uint2 d = *reinterpret_cast<const uint2 *>(P.id + i0);
-      w[0] = a.x; w[1] = i0 + 1 < end ? a.y : W_DEAD;
-      off[0] = o.x; off[1] = o.y; vx[0] = x.x; vx[1] = x.y; vy[0] = y.x; vy[1] = y.y; vz[0] = z.x; vz[1] = z.y;
-      id[0] = d.x; id[1] = d.y;
+      // the chunk starts on a multiple of 8 slots and the store is padded to 256,
+      // so the G slots from i0 are aligned and allocated; those past end are dead
+      if constexpr (G == 4) {
+        const int4 a = *reinterpret_cast<const int4 *>(P.w + i0);
+        const float4 o = *reinterpret_cast<const float4 *>(P.off + i0), x = *reinterpret_cast<const float4 *>(P.vx + i0),
+                     y = *reinterpret_cast<const float4 *>(P.vy + i0), z = *reinterpret_cast<const float4 *>(P.vz + i0);
+        const uint4 d = *reinterpret_cast<const uint4 *>(P.id + i0);
+        w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+        off[0] = o.x; off[1] = o.y; off[2] = o.z; off[3] = o.w;
+        vx[0] = x.x; vx[1] = x.y; vx[2] = x.z; vx[3] = x.w;
+        vy[0] = y.x; vy[1] = y.y; vy[2] = y.z; vy[3] = y.w;
+        vz[0] = z.x; vz[1] = z.y; vz[2] = z.z; vz[3] = z.w;
+        id[0] = d.x; id[1] = d.y; id[2] = d.z; id[3] = d.w;
+      } else {
+        const int2 a = *reinterpret_cast<const int2 *>(P.w + i0);
+        const float2 o = *reinterpret_cast<const float2 *>(P.off + i0), x = *reinterpret_cast<const float2 *>(P.vx + i0),
+                     y = *reinterpret_cast<const float2 *>(P.vy + i0), z = *reinterpret_cast<const float2 *>(P.vz + i0);
+        const uint2 d = *reinterpret_cast<const uint2 *>(P.id + i0);
+        w[0] = a.x; w[1] = a.y;
+        off[0] = o.x; off[1] = o.y; vx[0] = x.x; vx[1] = x.y; vy[0] = y.x; vy[1] = y.y; vz[0] = z.x; vz[1] = z.y;
+        id[0] = d.x; id[1] = d.y;
+      }
+#pragma unroll
+      for (int k = 1; k < G; ++k)
+        if (i0 + k >= end) w[k] = W_DEAD;
     }
     // live cell range of the tile
     int cl = 0x7FFFFFFF, ch = -1;
 #pragma unroll
-    for (int k = 0; k < SORT_G; ++k)
+    for (int k = 0; k < G; ++k)
       if (w[k] >= 0) { const int c = w[k] & (int32_t)W_CELL; cl = min(cl, c); ch = max(ch, c); }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) { cl = min(cl, __shfl_xor(cl, o, 64)); ch = max(ch, __shfl_xor(ch, o, 64)); }
@@ -1960,13 +1995,13 @@ __global__ __launch_bounds__(SORT_BS) void k_sort_scatter(Sim S, int s, Particle
       const int R = ch - cl + 1;
       for (int j = threadIdx.x; j < R; j += SORT_BS) t.cnt[j] = 0;
       __syncthreads();
-      int rank[SORT_G];
-      if (w[0] >= 0 && w[1] >= 0 && ((w[0] ^ w[1]) & (int32_t)W_CELL) == 0) {
-        rank[0] = atomicAdd(&t.cnt[(w[0] & (int32_t)W_CELL) - cl], 2);
+      int rank[G];
+      if (G == 2 && w[0] >= 0 && w[1] >= 0 && ((w[0] ^ w[1]) & (int32_t)W_CELL) == 0) {
+        rank[0] = atomicAdd(&t.cnt[(w[0] & (int32_t)W_CELL) - cl], 2);   // a pair in one cell: one reservation
         rank[1] = rank[0] + 1;
       } else {
 #pragma unroll
-        for (int k = 0; k < SORT_G; ++k)
+        for (int k = 0; k < G; ++k)
           if (w[k] >= 0) rank[k] = atomicAdd(&t.cnt[(w[k] & (int32_t)W_CELL) - cl], 1);
       }
       __syncthreads();
@@ -1982,7 +2017,7 @@ __global__ __launch_bounds__(SORT_BS) void k_sort_scatter(Sim S, int s, Particle
       }
       __syncthreads();
 #pragma unroll
-      for (int k = 0; k < SORT_G; ++k) {
+      for (int k = 0; k < G; ++k) {
         if (w[k] < 0) continue;
         const int pos = t.start[(w[k] & (int32_t)W_CELL) - cl] + rank[k];
         t.w[pos] = w[k]; t.off[pos] = off[k]; t.vx[pos] = vx[k]; t.vy[pos] = vy[k]; t.vz[pos] = vz[k];
@@ -1998,7 +2033,7 @@ __global__ __launch_bounds__(SORT_BS) void k_sort_scatter(Sim S, int s, Particle
       }
     } else if (ch >= 0) {
 #pragma unroll
-      for (int k = 0; k < SORT_G; ++k) {
+      for (int k = 0; k < G; ++k) {
         if (w[k] < 0) continue;
         const int c = w[k] & (int32_t)W_CELL;
         const int64_t d = (int64_t)lbase[c] + atomicAdd(&lfill[c], 1);
@@ -2538,8 +2573,8 @@ hipError_t set_lds_limits(const Sim &S, int block) {
     e = hipFuncSetAttribute((const void *)k_fixup<FBS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fixup_lds_bytes(S));
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_sort_scatter, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)sort_lds_bytes(S));
+    e = hipFuncSetAttribute(sort_tile_g(S) == 4 ? (const void *)k_sort_scatter<4> : (const void *)k_sort_scatter<2>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_lds_bytes(S));
   return e;
 }
 
@@ -2612,7 +2647,8 @@ hipError_t launch_sort(const Sim &S, int s, const Particles &dst, int grid, hipS
   grid = grid < SORT_GRID ? grid : SORT_GRID;      // count and scatter cut the same chunks
   hipLaunchKernelGGL((k_sort_count<FBS>), dim3(grid), dim3(FBS), sizeof(int) * S.ng, st, S, s);
   hipLaunchKernelGGL((k_sort_scan<FBS>), dim3(1), dim3(FBS), 0, st, S, s);
-  hipLaunchKernelGGL(k_sort_scatter, dim3(grid), dim3(SORT_BS), sort_lds_bytes(S), st, S, s, dst);
+  if (sort_tile_g(S) == 4) hipLaunchKernelGGL(k_sort_scatter<4>, dim3(grid), dim3(SORT_BS), sort_lds_bytes(S), st, S, s, dst);
+  else hipLaunchKernelGGL(k_sort_scatter<2>, dim3(grid), dim3(SORT_BS), sort_lds_bytes(S), st, S, s, dst);
   return hipGetLastError();
 }
 
