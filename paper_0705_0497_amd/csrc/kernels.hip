@@ -1921,11 +1921,14 @@ struct SortTile {
 template <int G>
 size_t sort_lds_bytes_g(const Sim &S) { return sizeof(SortTile<G>) + 2 * sizeof(int32_t) * (size_t)S.ng; }
 
-// tiles of 4096 where the block's LDS holds one beside the block's cell ranges
-// (up to 6632 cells), else of 2048
-int sort_tile_g(const Sim &S) { return sort_lds_bytes_g<4>(S) <= SORT_LDS_MAX ? 4 : 2; }
+// Electrons: tiles of 4096 where the block's LDS holds one beside the block's cell
+// ranges (up to 6632 cells), else of 2048.  Ions cross a few cells between two
+// sorts, so their tiles already write long runs and the smaller tile is faster.
+int sort_tile_g(const Sim &S, int s) { return s == 0 && sort_lds_bytes_g<4>(S) <= SORT_LDS_MAX ? 4 : 2; }
 
-size_t sort_lds_bytes(const Sim &S) { return sort_tile_g(S) == 4 ? sort_lds_bytes_g<4>(S) : sort_lds_bytes_g<2>(S); }
+size_t sort_lds_bytes(const Sim &S, int s) {
+  return sort_tile_g(S, s) == 4 ? sort_lds_bytes_g<4>(S) : sort_lds_bytes_g<2>(S);
+}
 
 template <int G>
 __global__ __launch_bounds__(SORT_BS) void k_sort_scatter(Sim S, int s, Particles dst) {
@@ -2573,8 +2576,11 @@ hipError_t set_lds_limits(const Sim &S, int block) {
     e = hipFuncSetAttribute((const void *)k_fixup<FBS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fixup_lds_bytes(S));
   if (e == hipSuccess)
-    e = hipFuncSetAttribute(sort_tile_g(S) == 4 ? (const void *)k_sort_scatter<4> : (const void *)k_sort_scatter<2>,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)sort_lds_bytes(S));
+    e = hipFuncSetAttribute((const void *)k_sort_scatter<2>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sort_lds_bytes_g<2>(S));
+  if (e == hipSuccess && sort_tile_g(S, 0) == 4)
+    e = hipFuncSetAttribute((const void *)k_sort_scatter<4>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)sort_lds_bytes_g<4>(S));
   return e;
 }
 
@@ -2647,8 +2653,9 @@ hipError_t launch_sort(const Sim &S, int s, const Particles &dst, int grid, hipS
   grid = grid < SORT_GRID ? grid : SORT_GRID;      // count and scatter cut the same chunks
   hipLaunchKernelGGL((k_sort_count<FBS>), dim3(grid), dim3(FBS), sizeof(int) * S.ng, st, S, s);
   hipLaunchKernelGGL((k_sort_scan<FBS>), dim3(1), dim3(FBS), 0, st, S, s);
-  if (sort_tile_g(S) == 4) hipLaunchKernelGGL(k_sort_scatter<4>, dim3(grid), dim3(SORT_BS), sort_lds_bytes(S), st, S, s, dst);
-  else hipLaunchKernelGGL(k_sort_scatter<2>, dim3(grid), dim3(SORT_BS), sort_lds_bytes(S), st, S, s, dst);
+  const size_t lds = sort_lds_bytes(S, s);
+  if (sort_tile_g(S, s) == 4) hipLaunchKernelGGL(k_sort_scatter<4>, dim3(grid), dim3(SORT_BS), lds, st, S, s, dst);
+  else hipLaunchKernelGGL(k_sort_scatter<2>, dim3(grid), dim3(SORT_BS), lds, st, S, s, dst);
   return hipGetLastError();
 }
 
